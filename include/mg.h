@@ -1,0 +1,153 @@
+/*
+ * mg.h -- C ABI of the MI355X (gfx950) GEMM library.
+ *
+ * The operation is the generalised matrix-matrix multiply of the Alpaka
+ * paper's evaluation (Section 4.2, "Performance"):
+ *
+ *     C <- alpha * A * B + beta * C,   A: m x k, B: k x n, C: m x n.
+ *
+ * Conventions shared by every entry point
+ *  - Matrices are row-major 1-D buffers with a row pitch ("leading dimension",
+ *    ld) in elements, ld >= number of columns: the paper's memory model of a
+ *    plain pointer plus extent plus pitch (Section 3.4, "Memory").
+ *  - All matrix pointers are DEVICE pointers owned by the caller.  The library
+ *    never allocates, frees, copies or migrates them (no implicit data
+ *    movement, Section 3.1).  Host arrays of descriptors are read during the
+ *    call only.
+ *  - `stream` is a hipStream_t passed as void*; work is enqueued on it in
+ *    order and the call returns without waiting (an asynchronous stream in the
+ *    paper's sense, Section 3.4, "Streams").  There is no default stream or
+ *    current-device assumption beyond HIP's own: the stream must belong to the
+ *    calling thread's current device.
+ *  - Return value: MG_OK (0) or a negative MG_ERR_* code.  Argument errors are
+ *    detected before anything is enqueued.  mg_last_error() returns a
+ *    thread-local message describing the most recent failure of the calling
+ *    thread.
+ *  - BLAS special cases: beta == 0 means C is not read (NaN in C does not
+ *    propagate); alpha == 0 or k == 0 means A and B are not read and
+ *    C <- beta*C; m == 0 or n == 0 is a no-op.
+ *  - The output C must not overlap A or B.
+ */
+#ifndef MG_H
+#define MG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define MG_OK 0
+#define MG_PENDING 1            /* mg_gemm_poll: request not finished yet     */
+#define MG_ERR_INVALID_ARG (-1) /* bad pointer/size/pitch/overlap/option      */
+#define MG_ERR_UNSUPPORTED (-2) /* dtype x algo combination not provided      */
+#define MG_ERR_HIP (-3)         /* HIP runtime error (message in last_error)  */
+#define MG_ERR_NO_MEMORY (-4)   /* request larger than the HBM budget, or a
+                                   device allocation failed                   */
+#define MG_ERR_BUSY (-5)        /* server queue full                          */
+#define MG_ERR_NOT_FOUND (-6)   /* unknown ticket                             */
+
+/* ------------------------------------------------------------ element types */
+#define MG_F64 0
+#define MG_F32 1
+
+/* -------------------------------------------------------------- algorithms */
+#define MG_NATIVE 0     /* FP64 (or FP32) MFMA tiled kernel                   */
+#define MG_SPLIT_I8 1   /* FP64 from INT8 slices, INT32 accumulation          */
+#define MG_SPLIT_BF16 2 /* FP64 from BF16-held 8-bit slices, FP32 accumulation */
+
+/* Message for the calling thread's most recent error ("" if none). The
+ * pointer stays valid until the thread's next library call. */
+const char *mg_last_error(void);
+
+/* Library ABI version (major*10000 + minor*100 + patch). */
+int mg_version(void);
+
+/* ------------------------------------------------------------ plain GEMM --
+ * mg_gemm: C <- alpha*A*B + beta*C (Section 4.2 problem statement).
+ *   dtype  MG_F64 (algo MG_NATIVE, MG_SPLIT_I8 or MG_SPLIT_BF16; the split
+ *          algorithms take FP64 in and out) or MG_F32 (MG_NATIVE only).
+ *   m,n,k  extents (>= 0).  lda >= k, ldb >= n, ldc >= n (elements).
+ *   A,B,C  device pointers to dtype elements, naturally aligned.
+ * The work division (macro-tile shape, i.e. blocks, threads per block and
+ * elements per thread in the paper's terms, Table 2 and Section 3.4) is
+ * chosen by the library from the shape.  The split algorithms use the
+ * default slice count (mg_split_default_slices) and take their workspace
+ * from HIP's stream-ordered allocator on `stream` (released on the same
+ * stream); use mg_gemm_split to supply the workspace instead. */
+int mg_gemm(int dtype, int algo, int64_t m, int64_t n, int64_t k, double alpha,
+            const void *A, int64_t lda, const void *B, int64_t ldb, double beta,
+            void *C, int64_t ldc, void *stream);
+
+/* Work divisions of the native kernel.  Configuration `cfg` in
+ * [0, mg_num_tile_cfgs()) is a macro-tile of bm x bn outputs per workgroup
+ * with a k-step of bk, computed by `threads` lanes.  Returns MG_OK or
+ * MG_ERR_INVALID_ARG for an unknown cfg; any output pointer may be NULL. */
+int mg_num_tile_cfgs(void);
+int mg_tile_cfg_info(int dtype, int cfg, int *bm, int *bn, int *bk, int *threads);
+
+/* mg_gemm with an explicit work division `cfg` (MG_NATIVE only).  Same
+ * arguments and errors as mg_gemm; MG_ERR_INVALID_ARG for an unknown cfg. */
+int mg_gemm_cfg(int dtype, int cfg, int64_t m, int64_t n, int64_t k, double alpha,
+                const void *A, int64_t lda, const void *B, int64_t ldb,
+                double beta, void *C, int64_t ldc, void *stream);
+
+/* The cfg mg_gemm picks for this shape (its work-division rule). */
+int mg_pick_tile_cfg(int dtype, int64_t m, int64_t n, int64_t k);
+
+/* ------------------------------------------------ split-precision FP64 --
+ * The FP64 product is rebuilt from exact integer slices (not part of the
+ * paper, which computes DGEMM natively; the splitting follows Ozaki et al.'s
+ * error-free transformation of matrix products):
+ *   1. E_i = frexp exponent of max_p |A[i][p]| (so |A[i][:]| < 2^E_i), F_j
+ *      likewise for column j of B; an all-zero row/column gets 0.
+ *   2. With r = x*2^-E and b = 7 (MG_SPLIT_I8) or 8 (MG_SPLIT_BF16), for
+ *      t = 1..s: y = r*2^b, slice_t = trunc(y), r = y - slice_t (all exact,
+ *      |slice_t| <= 2^b - 1).
+ *   3. P_d = sum over p+q = d of A_p*B_q for d = 2..s+1, exactly (INT8 x INT8
+ *      with INT32 accumulation, or BF16 x BF16 with FP32 accumulation over
+ *      256-long k chunks, both exact for the integers involved).
+ *   4. acc = sum_d P_d*2^(-b*d) in FP64, increasing d;
+ *      C <- alpha*(2^(E_i+F_j)*acc) + beta*C, each product and the sum
+ *      rounded once (no fused multiply-add).
+ * Finite inputs are assumed.  Error vs the exact product is bounded per
+ * element by |alpha| k 2^(E_i+F_j) (s+3) 2^(-b s) plus FP64 rounding.
+ *
+ * Workspace layout (bytes from the workspace base; all offsets 256-aligned):
+ *   mp, np, kp = m, n, k rounded up to 128 (at least 128)
+ *   int32 E[mp] at e_off, int32 F[np] at f_off (padding entries 0)
+ *   A slices at a_off: [s][mp][kp] row-major elements (INT8, or BF16 bits)
+ *   B slices at b_off: [s][np][kp], i.e. slice t of B transposed (k fastest)
+ *   padding (rows >= m, columns >= n, k >= k) is zero.
+ */
+typedef struct mg_split_layout {
+  int64_t mp, np, kp, elem_bytes;
+  int64_t e_off, f_off, a_off, b_off, total_bytes;
+} mg_split_layout;
+
+/* Default slice count: 7 for MG_SPLIT_I8, 6 for MG_SPLIT_BF16. */
+int mg_split_default_slices(int algo);
+
+/* Fills *out with the workspace layout; MG_ERR_INVALID_ARG for a bad algo,
+ * slices outside [1, 16] or negative extents. */
+int mg_split_layout_query(int algo, int slices, int64_t m, int64_t n, int64_t k,
+                          mg_split_layout *out);
+
+/* Steps 1-2: writes E, F and the slices of A and B into `workspace`
+ * (device memory of at least total_bytes, owned by the caller). */
+int mg_split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, const double *A,
+                     int64_t lda, const double *B, int64_t ldb, void *workspace,
+                     int64_t workspace_bytes, void *stream);
+
+/* Steps 1-4 with a caller-provided workspace: C <- alpha*A*B + beta*C. */
+int mg_gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
+                  const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+                  double *C, int64_t ldc, void *workspace, int64_t workspace_bytes,
+                  void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MG_H */

@@ -1,0 +1,206 @@
+"""Python binding of libmg, the MI355X (gfx950) GEMM library.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libmg.so.  PyTorch supplies device memory and streams.  If the
+shared library is missing this module raises on first use; there is no
+fallback path.
+
+The operation is the paper's DGEMM, C <- alpha*A*B + beta*C (Section 4.2),
+on row-major matrices with a row pitch (``tensor.stride(0)``).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmg.so")
+
+# status codes (include/mg.h)
+OK = 0
+PENDING = 1
+ERR_INVALID_ARG = -1
+ERR_UNSUPPORTED = -2
+ERR_HIP = -3
+ERR_NO_MEMORY = -4
+ERR_BUSY = -5
+ERR_NOT_FOUND = -6
+
+F64 = 0
+F32 = 1
+NATIVE = 0
+SPLIT_I8 = 1
+SPLIT_BF16 = 2
+
+
+class MgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libmg error {code}: {msg}")
+        self.code = code
+
+
+class SplitLayout(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("mp", "np", "kp", "elem_bytes", "e_off", "f_off", "a_off", "b_off",
+                 "total_bytes")]
+
+
+_lib = None
+_i64 = ctypes.c_int64
+_dbl = ctypes.c_double
+_vp = ctypes.c_void_p
+_int = ctypes.c_int
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libmg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.mg_last_error.restype = ctypes.c_char_p
+        L.mg_version.restype = _int
+        L.mg_num_tile_cfgs.restype = _int
+        L.mg_tile_cfg_info.argtypes = [_int, _int] + [ctypes.POINTER(_int)] * 4
+        L.mg_pick_tile_cfg.argtypes = [_int, _i64, _i64, _i64]
+        gemm_args = [_i64, _i64, _i64, _dbl, _vp, _i64, _vp, _i64, _dbl, _vp, _i64, _vp]
+        L.mg_gemm.argtypes = [_int, _int] + gemm_args
+        L.mg_gemm_cfg.argtypes = [_int, _int] + gemm_args
+        L.mg_split_default_slices.argtypes = [_int]
+        L.mg_split_layout_query.argtypes = [_int, _int, _i64, _i64, _i64,
+                                            ctypes.POINTER(SplitLayout)]
+        L.mg_split_prepare.argtypes = [_int, _int, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp,
+                                       _i64, _vp]
+        L.mg_gemm_split.argtypes = [_int, _int, _i64, _i64, _i64, _dbl, _vp, _i64, _vp, _i64,
+                                    _dbl, _vp, _i64, _vp, _i64, _vp]
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().mg_last_error().decode()
+
+
+def check(rc: int) -> int:
+    if rc < 0:
+        raise MgError(rc, last_error())
+    return rc
+
+
+# ------------------------------------------------------------------ helpers
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _mat(t, name):
+    """(pointer, rows, cols, ld) of a row-major 2-D tensor with unit column stride."""
+    if t is None:
+        return None, 0, 0, 1
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D")
+    if t.shape[1] > 1 and t.stride(1) != 1:
+        raise ValueError(f"{name} must have unit column stride (row-major)")
+    ld = t.stride(0) if t.shape[0] > 1 else max(t.shape[1], 1)
+    return ctypes.c_void_p(t.data_ptr()), t.shape[0], t.shape[1], max(ld, t.shape[1], 1)
+
+
+def _mnk(A, B, C, k):
+    pa, am, ak, lda = _mat(A, "A")
+    pb, bk, bn, ldb = _mat(B, "B")
+    pc, cm, cn, ldc = _mat(C, "C")
+    m, n = cm, cn
+    if A is not None:
+        k = ak
+        if am != m:
+            raise ValueError("A rows != C rows")
+    if B is not None:
+        if bn != n or bk != k:
+            raise ValueError("B shape mismatch")
+    return (pa, lda), (pb, ldb), (pc, ldc), m, n, k
+
+
+# --------------------------------------------------------------------- API
+def gemm(A, B, C, alpha: float = 1.0, beta: float = 0.0, algo: int = NATIVE,
+         cfg: int | None = None, stream=None, k: int | None = None):
+    """C <- alpha*A@B + beta*C in place on the GPU (mg_gemm / mg_gemm_cfg).
+    A may be None only with k == 0.  Returns C."""
+    (pa, lda), (pb, ldb), (pc, ldc), m, n, kk = _mnk(A, B, C, k)
+    dt = _dtype_code(C)
+    s = _stream_handle(stream)
+    if cfg is None:
+        check(lib().mg_gemm(dt, algo, m, n, kk, alpha, pa, lda, pb, ldb, beta, pc, ldc, s))
+    else:
+        check(lib().mg_gemm_cfg(dt, cfg, m, n, kk, alpha, pa, lda, pb, ldb, beta, pc, ldc, s))
+    return C
+
+
+def num_tile_cfgs() -> int:
+    return lib().mg_num_tile_cfgs()
+
+
+def tile_cfg_info(cfg: int, dtype: int = F64) -> dict:
+    v = [_int() for _ in range(4)]
+    check(lib().mg_tile_cfg_info(dtype, cfg, *[ctypes.byref(x) for x in v]))
+    return dict(zip(("bm", "bn", "bk", "threads"), (x.value for x in v)))
+
+
+def pick_tile_cfg(m: int, n: int, k: int, dtype: int = F64) -> int:
+    return lib().mg_pick_tile_cfg(dtype, m, n, k)
+
+
+def split_default_slices(algo: int) -> int:
+    return check(lib().mg_split_default_slices(algo))
+
+
+def split_layout(algo: int, slices: int, m: int, n: int, k: int) -> dict:
+    L = SplitLayout()
+    check(lib().mg_split_layout_query(algo, slices, m, n, k, ctypes.byref(L)))
+    return {f: getattr(L, f) for f, _ in SplitLayout._fields_}
+
+
+def split_workspace(algo: int, slices: int, m: int, n: int, k: int, device="cuda"):
+    """A uint8 device tensor large enough for mg_gemm_split's workspace."""
+    import torch
+    return torch.empty(split_layout(algo, slices, m, n, k)["total_bytes"], dtype=torch.uint8,
+                       device=device)
+
+
+def split_prepare(algo: int, slices: int, A, B, workspace, stream=None):
+    """Steps 1-2 of the split method into ``workspace`` (mg_split_prepare)."""
+    pa, m, k, lda = _mat(A, "A")
+    pb, kb, n, ldb = _mat(B, "B")
+    if kb != k:
+        raise ValueError("inner dimensions differ")
+    check(lib().mg_split_prepare(algo, slices, m, n, k, pa, lda, pb, ldb,
+                                 ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                 _stream_handle(stream)))
+    return workspace
+
+
+def gemm_split(A, B, C, alpha: float = 1.0, beta: float = 0.0, algo: int = SPLIT_I8,
+               slices: int | None = None, workspace=None, stream=None):
+    """C <- alpha*A@B + beta*C through the split-precision path (mg_gemm_split)."""
+    (pa, lda), (pb, ldb), (pc, ldc), m, n, k = _mnk(A, B, C, None)
+    if slices is None:
+        slices = split_default_slices(algo)
+    if workspace is None:
+        workspace = split_workspace(algo, slices, m, n, k, device=C.device)
+    check(lib().mg_gemm_split(algo, slices, m, n, k, alpha, pa, lda, pb, ldb, beta, pc, ldc,
+                              ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                              _stream_handle(stream)))
+    return C

@@ -1,0 +1,238 @@
+// extern "C" boundary of libmg: argument validation, error reporting and
+// dispatch to the kernels.  Nothing is enqueued when validation fails.
+#include <algorithm>
+#include <cstdarg>
+#include <cstring>
+
+#include "common.h"
+#include "gemm_native.h"
+#include "split.h"
+
+namespace mg {
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+void set_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+void clear_error() { g_err[0] = '\0'; }
+
+int validate_problem(const char *what, int64_t m, int64_t n, int64_t k, double alpha,
+                     const void *A, int64_t lda, const void *B, int64_t ldb, double beta,
+                     const void *C, int64_t ldc, int64_t esz) {
+  (void)beta;
+  if (m < 0 || n < 0 || k < 0) {
+    set_error("%s: negative extent (m=%lld n=%lld k=%lld)", what, (long long)m, (long long)n,
+              (long long)k);
+    return MG_ERR_INVALID_ARG;
+  }
+  // Extents index with 32-bit ints inside tiles; pitches and offsets are 64-bit.
+  const int64_t lim = (int64_t)1 << 30;
+  if (m >= lim || n >= lim || k >= lim) {
+    set_error("%s: extent too large (limit 2^30)", what);
+    return MG_ERR_INVALID_ARG;
+  }
+  if (m == 0 || n == 0) return MG_OK;
+  if (C == nullptr) {
+    set_error("%s: C is NULL", what);
+    return MG_ERR_INVALID_ARG;
+  }
+  if (ldc < n) {
+    set_error("%s: ldc=%lld < n=%lld", what, (long long)ldc, (long long)n);
+    return MG_ERR_INVALID_ARG;
+  }
+  if (reinterpret_cast<uintptr_t>(C) % (uintptr_t)esz) {
+    set_error("%s: C not aligned to its element size", what);
+    return MG_ERR_INVALID_ARG;
+  }
+  const int64_t big = (int64_t)1 << 62;
+  if ((m - 1) > big / ldc) {
+    set_error("%s: C extent overflows", what);
+    return MG_ERR_INVALID_ARG;
+  }
+  const bool reads_ab = k > 0 && alpha != 0.0;
+  if (!reads_ab) return MG_OK;
+  if (A == nullptr || B == nullptr) {
+    set_error("%s: A or B is NULL", what);
+    return MG_ERR_INVALID_ARG;
+  }
+  if (lda < k) {
+    set_error("%s: lda=%lld < k=%lld", what, (long long)lda, (long long)k);
+    return MG_ERR_INVALID_ARG;
+  }
+  if (ldb < n) {
+    set_error("%s: ldb=%lld < n=%lld", what, (long long)ldb, (long long)n);
+    return MG_ERR_INVALID_ARG;
+  }
+  if (reinterpret_cast<uintptr_t>(A) % (uintptr_t)esz ||
+      reinterpret_cast<uintptr_t>(B) % (uintptr_t)esz) {
+    set_error("%s: A or B not aligned to its element size", what);
+    return MG_ERR_INVALID_ARG;
+  }
+  if ((m - 1) > big / lda || (k - 1) > big / ldb) {
+    set_error("%s: A or B extent overflows", what);
+    return MG_ERR_INVALID_ARG;
+  }
+  if (spans_overlap(C, m, n, ldc, A, m, k, lda, esz) ||
+      spans_overlap(C, m, n, ldc, B, k, n, ldb, esz)) {
+    set_error("%s: C overlaps A or B", what);
+    return MG_ERR_INVALID_ARG;
+  }
+  return MG_OK;
+}
+
+static int64_t esize(int dtype) { return dtype == MG_F64 ? 8 : dtype == MG_F32 ? 4 : 0; }
+
+}  // namespace mg
+
+using namespace mg;
+
+extern "C" {
+
+const char *mg_last_error(void) { return g_err; }
+
+int mg_version(void) { return 10000; }
+
+int mg_num_tile_cfgs(void) { return num_tile_cfgs(); }
+
+int mg_tile_cfg_info(int dtype, int cfg, int *bm, int *bn, int *bk, int *threads) {
+  clear_error();
+  return tile_cfg_info(dtype, cfg, bm, bn, bk, threads);
+}
+
+int mg_pick_tile_cfg(int dtype, int64_t m, int64_t n, int64_t k) {
+  return pick_tile_cfg(dtype, m, n, k);
+}
+
+int mg_gemm_cfg(int dtype, int cfg, int64_t m, int64_t n, int64_t k, double alpha, const void *A,
+                int64_t lda, const void *B, int64_t ldb, double beta, void *C, int64_t ldc,
+                void *stream) {
+  clear_error();
+  const int64_t es = esize(dtype);
+  if (es == 0) {
+    set_error("unknown dtype %d", dtype);
+    return MG_ERR_INVALID_ARG;
+  }
+  if (cfg < 0 || cfg >= num_tile_cfgs()) {
+    set_error("unknown tile cfg %d", cfg);
+    return MG_ERR_INVALID_ARG;
+  }
+  int rc = validate_problem("gemm", m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, es);
+  if (rc != MG_OK) return rc;
+  return gemm_native(dtype, cfg, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                     static_cast<hipStream_t>(stream));
+}
+
+int mg_gemm(int dtype, int algo, int64_t m, int64_t n, int64_t k, double alpha, const void *A,
+            int64_t lda, const void *B, int64_t ldb, double beta, void *C, int64_t ldc,
+            void *stream) {
+  clear_error();
+  const int64_t es = esize(dtype);
+  if (es == 0) {
+    set_error("unknown dtype %d", dtype);
+    return MG_ERR_INVALID_ARG;
+  }
+  if (algo != MG_NATIVE && algo != MG_SPLIT_I8 && algo != MG_SPLIT_BF16) {
+    set_error("unknown algo %d", algo);
+    return MG_ERR_INVALID_ARG;
+  }
+  if (algo != MG_NATIVE && dtype != MG_F64) {
+    set_error("split algorithms take FP64 operands");
+    return MG_ERR_UNSUPPORTED;
+  }
+  int rc = validate_problem("gemm", m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, es);
+  if (rc != MG_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (algo == MG_NATIVE)
+    return gemm_native(dtype, pick_tile_cfg(dtype, m, n, k), m, n, k, alpha, A, lda, B, ldb,
+                       beta, C, ldc, s);
+  return gemm_split_pooled(algo, split_default_slices(algo), m, n, k, alpha,
+                           static_cast<const double *>(A), lda, static_cast<const double *>(B),
+                           ldb, beta, static_cast<double *>(C), ldc, s);
+}
+
+int mg_split_default_slices(int algo) {
+  clear_error();
+  if (algo != MG_SPLIT_I8 && algo != MG_SPLIT_BF16) {
+    set_error("not a split algorithm: %d", algo);
+    return MG_ERR_INVALID_ARG;
+  }
+  return split_default_slices(algo);
+}
+
+int mg_split_layout_query(int algo, int slices, int64_t m, int64_t n, int64_t k,
+                          mg_split_layout *out) {
+  clear_error();
+  if (out == nullptr) {
+    set_error("out is NULL");
+    return MG_ERR_INVALID_ARG;
+  }
+  SplitLayout L;
+  int rc = split_layout(algo, slices, m, n, k, &L);
+  if (rc != MG_OK) return rc;
+  out->mp = L.mp;
+  out->np = L.np;
+  out->kp = L.kp;
+  out->elem_bytes = L.elem_bytes;
+  out->e_off = L.e_off;
+  out->f_off = L.f_off;
+  out->a_off = L.a_off;
+  out->b_off = L.b_off;
+  out->total_bytes = L.total;
+  return MG_OK;
+}
+
+int mg_split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, const double *A,
+                     int64_t lda, const double *B, int64_t ldb, void *workspace,
+                     int64_t workspace_bytes, void *stream) {
+  clear_error();
+  SplitLayout L;
+  int rc = split_layout(algo, slices, m, n, k, &L);
+  if (rc != MG_OK) return rc;
+  // Validate A and B as operands of an m x n product (C is not touched).
+  double dummy = 0.0;
+  rc = validate_problem("split_prepare", std::max<int64_t>(m, 1), std::max<int64_t>(n, 1), k, 1.0,
+                        A, lda, B, ldb, 0.0, &dummy, std::max<int64_t>(n, 1), 8);
+  if (rc != MG_OK) return rc;
+  if (workspace == nullptr || workspace_bytes < L.total) {
+    set_error("split workspace too small: need %lld bytes", (long long)L.total);
+    return MG_ERR_INVALID_ARG;
+  }
+  if (k > 0 && (A == nullptr || B == nullptr)) {
+    set_error("A or B is NULL");
+    return MG_ERR_INVALID_ARG;
+  }
+  return split_prepare(algo, slices, m, n, k, A, lda, B, ldb, workspace,
+                       static_cast<hipStream_t>(stream));
+}
+
+int mg_gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
+                  const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+                  double *C, int64_t ldc, void *workspace, int64_t workspace_bytes,
+                  void *stream) {
+  clear_error();
+  SplitLayout L;
+  int rc = split_layout(algo, slices, m, n, k, &L);
+  if (rc != MG_OK) return rc;
+  rc = validate_problem("gemm_split", m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, 8);
+  if (rc != MG_OK) return rc;
+  if (workspace != nullptr) {
+    const bool reads_ab = k > 0 && alpha != 0.0;
+    if ((reads_ab && spans_overlap(workspace, 1, workspace_bytes, workspace_bytes, C, m, n, ldc, 8)) ||
+        (reads_ab && spans_overlap(workspace, 1, workspace_bytes, workspace_bytes, A, m, k, lda, 8)) ||
+        (reads_ab && spans_overlap(workspace, 1, workspace_bytes, workspace_bytes, B, k, n, ldb, 8))) {
+      set_error("workspace overlaps A, B or C");
+      return MG_ERR_INVALID_ARG;
+    }
+  }
+  return gemm_split(algo, slices, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, workspace,
+                    workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

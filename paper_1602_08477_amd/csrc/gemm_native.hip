@@ -1,0 +1,153 @@
+// Native FP64 / FP32 GEMM: one workgroup per macro-tile of C (Section 4.2.2
+// tiling), work division chosen per shape on the host.
+#include "gemm_native.h"
+
+#include "gemm_tile.h"
+
+namespace mg {
+
+namespace {
+
+constexpr int kGroupM = 8;  // tile-rows walked together by the raster
+
+template <typename T, int BM, int BN, bool VEC_OK>
+__global__ __launch_bounds__(kTileThreads) void gemm_native_kernel(GemmArgs<T> g, int tiles_m,
+                                                                   int tiles_n) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T *smem = reinterpret_cast<T *>(lds_raw);
+  int tm, tn;
+  const int t = xcd_remap(blockIdx.x, tiles_m * tiles_n);
+  grouped_tile(t, tiles_m, tiles_n, kGroupM, tm, tn);
+  gemm_tile<T, BM, BN, VEC_OK>(g, tm * BM, tn * BN, smem);
+}
+
+// C <- beta*C (alpha == 0 or k == 0).  beta == 0 writes zeros without reading.
+template <typename T>
+__global__ void scale_kernel(T *C, int64_t ldc, int m, int n, T beta) {
+  const int64_t total = (int64_t)m * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / n, j = e % n;
+    T *p = C + i * ldc + j;
+    *p = beta == T(0) ? T(0) : beta * *p;
+  }
+}
+
+struct CfgDesc {
+  int bm, bn;
+};
+constexpr CfgDesc kCfgs[] = {{128, 128}, {128, 64}, {64, 64}, {64, 32}, {32, 32}};
+constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
+
+template <typename T, int BM, int BN, bool VEC_OK>
+int launch_one(const GemmArgs<T> &g, hipStream_t s) {
+  typedef TileShape<T, BM, BN> S;
+  const int tiles_m = (g.m + BM - 1) / BM, tiles_n = (g.n + BN - 1) / BN;
+  const int64_t tiles = (int64_t)tiles_m * tiles_n;
+  if (tiles > INT32_MAX) {
+    set_error("too many tiles (%lld)", (long long)tiles);
+    return MG_ERR_INVALID_ARG;
+  }
+  auto kern = gemm_native_kernel<T, BM, BN, VEC_OK>;
+  static bool attr_set = false;  // per template instance
+  if (!attr_set) {
+    MG_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)S::LDS_BYTES));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(kTileThreads), S::LDS_BYTES, s, g,
+                     tiles_m, tiles_n);
+  MG_HIP_TRY(hipGetLastError());
+  return MG_OK;
+}
+
+template <typename T, bool VEC_OK>
+int launch_cfg(int cfg, const GemmArgs<T> &g, hipStream_t s) {
+  switch (cfg) {
+    case 0: return launch_one<T, 128, 128, VEC_OK>(g, s);
+    case 1: return launch_one<T, 128, 64, VEC_OK>(g, s);
+    case 2: return launch_one<T, 64, 64, VEC_OK>(g, s);
+    case 3: return launch_one<T, 64, 32, VEC_OK>(g, s);
+    case 4: return launch_one<T, 32, 32, VEC_OK>(g, s);
+  }
+  set_error("unknown tile cfg %d", cfg);
+  return MG_ERR_INVALID_ARG;
+}
+
+template <typename T>
+int gemm_native_t(int cfg, int64_t m, int64_t n, int64_t k, double alpha, const void *A,
+                  int64_t lda, const void *B, int64_t ldb, double beta, void *C, int64_t ldc,
+                  hipStream_t s) {
+  if (m == 0 || n == 0) return MG_OK;
+  if (alpha == 0.0 || k == 0) {
+    const int64_t total = m * n;
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(scale_kernel<T>, dim3(blocks), dim3(256), 0, s, static_cast<T *>(C), ldc,
+                       (int)m, (int)n, (T)beta);
+    MG_HIP_TRY(hipGetLastError());
+    return MG_OK;
+  }
+  GemmArgs<T> g;
+  g.A = static_cast<const T *>(A);
+  g.B = static_cast<const T *>(B);
+  g.C = static_cast<T *>(C);
+  g.lda = lda;
+  g.ldb = ldb;
+  g.ldc = ldc;
+  g.m = (int)m;
+  g.n = (int)n;
+  g.k = (int)k;
+  g.alpha = (T)alpha;
+  g.beta = (T)beta;
+  constexpr int VEC = Mfma<T>::VEC;
+  const bool vec_ok = vec_aligned(A, lda, sizeof(T), VEC) &&
+                      vec_aligned(B, ldb, sizeof(T), VEC) && vec_aligned(C, ldc, sizeof(T), VEC);
+  return vec_ok ? launch_cfg<T, true>(cfg, g, s) : launch_cfg<T, false>(cfg, g, s);
+}
+
+}  // namespace
+
+bool vec_aligned(const void *p, int64_t ld, int64_t esz, int vec) {
+  return (reinterpret_cast<uintptr_t>(p) % (uintptr_t)(esz * vec)) == 0 && ld % vec == 0;
+}
+
+int num_tile_cfgs() { return kNumCfgs; }
+
+int tile_cfg_info(int dtype, int cfg, int *bm, int *bn, int *bk, int *threads) {
+  if (cfg < 0 || cfg >= kNumCfgs || (dtype != MG_F64 && dtype != MG_F32)) {
+    set_error("unknown tile cfg %d / dtype %d", cfg, dtype);
+    return MG_ERR_INVALID_ARG;
+  }
+  if (bm) *bm = kCfgs[cfg].bm;
+  if (bn) *bn = kCfgs[cfg].bn;
+  if (bk) *bk = dtype == MG_F64 ? Mfma<double>::BK : Mfma<float>::BK;
+  if (threads) *threads = kTileThreads;
+  return MG_OK;
+}
+
+int pick_tile_cfg(int dtype, int64_t m, int64_t n, int64_t k) {
+  (void)dtype;
+  (void)k;
+  // Largest tile that still gives every CU at least two workgroups; the
+  // smallest tile otherwise.
+  const int64_t want = 2 * 256;
+  for (int c = 0; c < kNumCfgs; ++c) {
+    const int64_t tiles = ceil_div(m, kCfgs[c].bm) * ceil_div(n, kCfgs[c].bn);
+    if (tiles >= want) return c;
+  }
+  return kNumCfgs - 1;
+}
+
+int gemm_native(int dtype, int cfg, int64_t m, int64_t n, int64_t k, double alpha, const void *A,
+                int64_t lda, const void *B, int64_t ldb, double beta, void *C, int64_t ldc,
+                hipStream_t s) {
+  if (dtype == MG_F64)
+    return gemm_native_t<double>(cfg, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s);
+  if (dtype == MG_F32)
+    return gemm_native_t<float>(cfg, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s);
+  set_error("unknown dtype %d", dtype);
+  return MG_ERR_INVALID_ARG;
+}
+
+}  // namespace mg

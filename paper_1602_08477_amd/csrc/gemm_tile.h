@@ -1,0 +1,296 @@
+// One macro-tile of C <- alpha*A*B + beta*C on gfx950 matrix cores.
+//
+// This is the hierarchical tiling of the paper's single-source DGEMM
+// (Section 4.2.2, Fig. 7): a block (workgroup) owns one tile of C, its
+// threads stage tiles of A and B in shared memory (LDS), every thread
+// accumulates a set of elements, and the block then moves on to the next
+// A/B tiles along k.  Mapped to CDNA4:
+//   grid    -> one dispatch (or a persistent loop over tiles)
+//   block   -> workgroup of 256 lanes = 4 wavefronts in a 2 x 2 arrangement
+//   thread  -> lane; its registers hold (BM/32)*(BN/32) MFMA accumulators
+//   element -> 16x16 MFMA fragments (4 values per lane) and 16-byte loads
+// A and B are double buffered in LDS: the global loads of k-tile t+1 are in
+// flight while the matrix cores work on tile t, with one barrier per tile.
+//
+// LDS layouts (chosen for conflict-free 16-byte LDS traffic):
+//   A: [BK/VEC][BM+2][VEC]  -- VEC = 16/sizeof(T) consecutive k values of one
+//      row form one 16-byte chunk, written as loaded from row-major A and read
+//      back with one ds_read_b128 that feeds VEC MFMAs.
+//   B: [BK][BN+PB]          -- row-major like B in HBM.
+// Fragment k mapping: lane group g = lane/16 supplies k = VEC*(4r+g)+v to the
+// v-th MFMA of round r on both operands, so A and B always agree on k.
+#pragma once
+
+#include "common.h"
+
+namespace mg {
+
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<double> {
+  typedef d4v acc_t;
+  typedef d2v vec_t;  // one 16-byte chunk
+  static constexpr int VEC = 2;
+  static constexpr int BK = 16;
+  static constexpr int PB = 8;  // B row pitch = BN + 8 doubles
+  // Row (within the 16x16 block) of accumulator register r of lane group g.
+  __device__ static __forceinline__ int row_of(int g, int r) { return 4 * r + g; }
+  __device__ static __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct Mfma<float> {
+  typedef f4v acc_t;
+  typedef f4v vec_t;
+  static constexpr int VEC = 4;
+  static constexpr int BK = 32;
+  static constexpr int PB = 4;
+  __device__ static __forceinline__ int row_of(int g, int r) { return 4 * g + r; }
+  __device__ static __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+template <typename T>
+struct GemmArgs {
+  const T *A;
+  const T *B;
+  T *C;
+  int64_t lda, ldb, ldc;
+  int m, n, k;
+  T alpha, beta;
+};
+
+constexpr int kTileThreads = 256;
+
+template <typename T, int BM, int BN>
+struct TileShape {
+  typedef Mfma<T> M;
+  static constexpr int VEC = M::VEC;
+  static constexpr int BK = M::BK;
+  static constexpr int PA = 2;  // A chunk-row pitch = BM + 2 chunks
+  static constexpr int PB = M::PB;
+  static constexpr int WM = BM / 2, WN = BN / 2;  // wave tile
+  static constexpr int FM = WM / 16, FN = WN / 16;  // MFMA blocks per wave
+  static constexpr int A_CHUNKS = BM * BK / VEC;  // 16-byte chunks per A tile
+  static constexpr int B_CHUNKS = BK * BN / VEC;
+  static constexpr int NA = A_CHUNKS / kTileThreads;  // per thread
+  static constexpr int NB = B_CHUNKS / kTileThreads;
+  static constexpr int A_STAGE = (BK / VEC) * (BM + PA) * VEC;  // elements
+  static constexpr int B_STAGE = BK * (BN + PB);
+  static constexpr int STAGE = A_STAGE + B_STAGE;
+  static constexpr size_t LDS_BYTES = 2 * STAGE * sizeof(T);
+  static_assert(BM % 32 == 0 && BN % 32 == 0, "tile must be a multiple of 32");
+  static_assert(NA >= 1 && NB >= 1 && A_CHUNKS % kTileThreads == 0 &&
+                    B_CHUNKS % kTileThreads == 0,
+                "every thread loads whole chunks");
+  static_assert((BK / VEC) % 4 == 0, "k rounds of 4 lane groups");
+};
+
+// Loads one 16-byte chunk of a row: `left` elements remain in the row from p.
+template <typename T, bool VEC_OK>
+__device__ __forceinline__ typename Mfma<T>::vec_t load_chunk(const T *p, bool ok, int left) {
+  typedef typename Mfma<T>::vec_t V;
+  constexpr int VEC = Mfma<T>::VEC;
+  V r = {};
+  if (VEC_OK && ok && left >= VEC) {
+    r = *reinterpret_cast<const V *>(p);
+  } else if (ok) {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v)
+      if (v < left) r[v] = p[v];
+  }
+  return r;
+}
+
+// Swap with the neighbouring lane (lane ^ 1) through DPP quad_perm [1,0,3,2].
+__device__ __forceinline__ double dpp_swap1(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  const int lo2 = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);
+  const int hi2 = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false);
+  return __hiloint2double(hi2, lo2);
+}
+
+// C tile epilogue for one 16x16 block: out = alpha*acc + beta*C (C unread
+// when beta == 0).  Lane l holds column l%16 of rows row_of(l/16, r).  FP64:
+// neighbouring lanes (same rows, columns j and j+1) swap one value each so
+// that each lane writes a 16-byte pair of adjacent columns of one row.
+template <typename T, bool VEC_OK>
+struct Epilogue;
+
+template <bool VEC_OK>
+struct Epilogue<double, VEC_OK> {
+  __device__ static __forceinline__ void store(const GemmArgs<double> &g, d4v acc, int row0,
+                                               int col0, int lane) {
+    const int gq = lane >> 4, j = lane & 15;
+    const bool odd = j & 1;
+    const int col = col0 + (j & ~1);
+#pragma unroll
+    for (int r = 0; r < 4; r += 2) {
+      const double send = odd ? acc[r] : acc[r + 1];
+      const double got = dpp_swap1(send);
+      const int row = row0 + Mfma<double>::row_of(gq, r + (odd ? 1 : 0));
+      d2v v;
+      v[0] = odd ? got : acc[r];
+      v[1] = odd ? acc[r + 1] : got;
+      if (row >= g.m) continue;
+      double *p = g.C + (int64_t)row * g.ldc + col;
+      if (VEC_OK && col + 1 < g.n) {
+        d2v c = {0.0, 0.0};
+        if (g.beta != 0.0) c = *reinterpret_cast<const d2v *>(p);
+        d2v o;
+        o[0] = g.beta != 0.0 ? fma(g.alpha, v[0], g.beta * c[0]) : g.alpha * v[0];
+        o[1] = g.beta != 0.0 ? fma(g.alpha, v[1], g.beta * c[1]) : g.alpha * v[1];
+        *reinterpret_cast<d2v *>(p) = o;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          if (col + e < g.n) {
+            const double o = g.beta != 0.0 ? fma(g.alpha, v[e], g.beta * p[e]) : g.alpha * v[e];
+            p[e] = o;
+          }
+        }
+      }
+    }
+  }
+};
+
+template <bool VEC_OK>
+struct Epilogue<float, VEC_OK> {
+  __device__ static __forceinline__ void store(const GemmArgs<float> &g, f4v acc, int row0,
+                                               int col0, int lane) {
+    const int gq = lane >> 4, j = lane & 15;
+    const int col = col0 + j;
+    if (col >= g.n) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row0 + Mfma<float>::row_of(gq, r);
+      if (row >= g.m) continue;
+      float *p = g.C + (int64_t)row * g.ldc + col;
+      *p = g.beta != 0.0f ? fmaf(g.alpha, acc[r], g.beta * *p) : g.alpha * acc[r];
+    }
+  }
+};
+
+// Computes the BM x BN tile of C whose top-left output is (m0, n0).
+// `smem` holds 2 stages of TileShape::STAGE elements.  All 256 lanes of the
+// workgroup must call this together (it contains barriers).
+template <typename T, int BM, int BN, bool VEC_OK>
+__device__ __forceinline__ void gemm_tile(const GemmArgs<T> &g, int m0, int n0, T *smem) {
+  typedef TileShape<T, BM, BN> S;
+  typedef Mfma<T> M;
+  typedef typename M::vec_t V;
+  typedef typename M::acc_t Acc;
+  constexpr int VEC = S::VEC, BK = S::BK;
+  constexpr int ACH = BK / VEC;  // A chunks per tile row
+  constexpr int BCH = BN / VEC;  // B chunks per tile row
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave >> 1) * S::WM, wn0 = (wave & 1) * S::WN;
+  const int gq = lane >> 4, l16 = lane & 15;
+
+  // Per-thread global chunk coordinates (fixed across k-tiles).
+  const T *pa[S::NA];
+  bool a_ok[S::NA];
+  int a_kc[S::NA], a_row[S::NA];
+#pragma unroll
+  for (int u = 0; u < S::NA; ++u) {
+    const int q = tid + kTileThreads * u;
+    a_row[u] = q / ACH;
+    a_kc[u] = q % ACH;
+    const int grow = m0 + a_row[u];
+    a_ok[u] = grow < g.m;
+    pa[u] = g.A + (int64_t)(a_ok[u] ? grow : 0) * g.lda + a_kc[u] * VEC;
+  }
+  const T *pb[S::NB];
+  bool b_ok[S::NB];
+  int b_r[S::NB], b_c[S::NB], b_left[S::NB];
+#pragma unroll
+  for (int u = 0; u < S::NB; ++u) {
+    const int q = tid + kTileThreads * u;
+    b_r[u] = q / BCH;
+    b_c[u] = (q % BCH) * VEC;
+    const int gcol = n0 + b_c[u];
+    b_ok[u] = gcol < g.n;
+    b_left[u] = g.n - gcol;
+    pb[u] = g.B + (int64_t)b_r[u] * g.ldb + (b_ok[u] ? gcol : 0);
+  }
+
+  V ra[S::NA], rb[S::NB];
+  auto load_tiles = [&](int kt) {
+    const int kbase = kt * BK;
+#pragma unroll
+    for (int u = 0; u < S::NA; ++u) {
+      const int kk = kbase + a_kc[u] * VEC;
+      ra[u] = load_chunk<T, VEC_OK>(pa[u] + kbase, a_ok[u], g.k - kk);
+    }
+#pragma unroll
+    for (int u = 0; u < S::NB; ++u) {
+      const int kr = kbase + b_r[u];
+      rb[u] = load_chunk<T, VEC_OK>(pb[u] + (int64_t)kbase * g.ldb, b_ok[u] && kr < g.k,
+                                    b_left[u]);
+    }
+  };
+  auto store_tiles = [&](int stage) {
+    T *As = smem + stage * S::STAGE;
+    T *Bs = As + S::A_STAGE;
+#pragma unroll
+    for (int u = 0; u < S::NA; ++u)
+      *reinterpret_cast<V *>(As + (a_kc[u] * (BM + S::PA) + a_row[u]) * VEC) = ra[u];
+#pragma unroll
+    for (int u = 0; u < S::NB; ++u)
+      *reinterpret_cast<V *>(Bs + b_r[u] * (BN + S::PB) + b_c[u]) = rb[u];
+  };
+
+  Acc acc[S::FM][S::FN];
+#pragma unroll
+  for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < S::FN; ++j) acc[i][j] = Acc{};
+
+  const int KT = (g.k + BK - 1) / BK;
+  if (KT > 0) {
+    load_tiles(0);
+    store_tiles(0);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < KT; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < KT) load_tiles(kt + 1);
+    const T *As = smem + cur * S::STAGE;
+    const T *Bs = As + S::A_STAGE;
+#pragma unroll
+    for (int r = 0; r < ACH / 4; ++r) {
+      const int kc = 4 * r + gq;  // this lane group's chunk
+      V a[S::FM];
+#pragma unroll
+      for (int i = 0; i < S::FM; ++i)
+        a[i] = *reinterpret_cast<const V *>(As + (kc * (BM + S::PA) + wm0 + 16 * i + l16) * VEC);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        T b[S::FN];
+#pragma unroll
+        for (int j = 0; j < S::FN; ++j) b[j] = Bs[(kc * VEC + v) * (BN + S::PB) + wn0 + 16 * j + l16];
+#pragma unroll
+        for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+          for (int j = 0; j < S::FN; ++j) acc[i][j] = M::mma(a[i][v], b[j], acc[i][j]);
+      }
+    }
+    if (kt + 1 < KT) store_tiles(cur ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < S::FN; ++j)
+      Epilogue<T, VEC_OK>::store(g, acc[i][j], m0 + wm0 + 16 * i, n0 + wn0 + 16 * j, lane);
+}
+
+}  // namespace mg

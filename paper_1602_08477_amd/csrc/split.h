@@ -1,0 +1,45 @@
+// Split-precision FP64 GEMM: FP64 operands are cut into exact integer slices
+// with per-row (A) and per-column (B) power-of-two scales, the slice products
+// run on INT8 (INT32 accumulation) or BF16 (FP32 accumulation) matrix cores,
+// and FP64 is used only for scaling, slicing and the final recombination.
+#pragma once
+
+#include "common.h"
+
+namespace mg {
+
+// Padding granularity of the workspace copies (rows of A, columns of B, k).
+constexpr int kSplitTile = 128;
+constexpr int kSplitMaxSlices = 16;
+
+struct SplitLayout {
+  int64_t mp, np, kp;    // padded extents
+  int64_t elem_bytes;    // 1 (INT8 slices) or 2 (BF16 slices)
+  int64_t e_off, f_off;  // int32 exponents of A rows [mp], B columns [np]
+  int64_t a_off, b_off;  // A slices [s][mp][kp], B slices [s][np][kp] (B transposed)
+  int64_t total;         // bytes
+};
+
+int split_default_slices(int algo);
+int split_bits(int algo);
+int split_layout(int algo, int slices, int64_t m, int64_t n, int64_t k, SplitLayout *L);
+
+// Scales + slices of A and B into the workspace (validated arguments).
+int split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, const double *A,
+                  int64_t lda, const double *B, int64_t ldb, void *ws, hipStream_t s);
+
+// Slice products + recombination + epilogue from a prepared workspace.
+int split_multiply(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
+                   double beta, double *C, int64_t ldc, const void *ws, hipStream_t s);
+
+// prepare + multiply with a caller-provided workspace.
+int gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
+               const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+               double *C, int64_t ldc, void *ws, int64_t ws_bytes, hipStream_t s);
+
+// The same with a workspace from HIP's stream-ordered allocator on `s`.
+int gemm_split_pooled(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
+                      const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+                      double *C, int64_t ldc, hipStream_t s);
+
+}  // namespace mg

@@ -1,0 +1,565 @@
+// Split-precision FP64 GEMM on INT8 / BF16 matrix cores.
+//
+// The method (an error-free splitting in the style of Ozaki et al.; not part
+// of the Alpaka paper, which computes DGEMM natively):
+//  1. E_i = frexp exponent of max_p |A[i,p]| (so |A[i,:]| < 2^E_i), F_j the
+//     same for column j of B; zero rows/columns get 0.
+//  2. r = x * 2^-E;  for t = 1..s:  y = r * 2^b,  slice_t = trunc(y),
+//     r = y - slice_t.  All exact; |slice| <= 2^b - 1 (b = 7 for INT8,
+//     b = 8 for BF16, whose 8-bit significand holds such integers exactly).
+//  3. P_d = sum_{p+q=d} A_p B_q for d = 2..s+1 (exact integers: INT32
+//     accumulation for INT8; FP32 accumulation over 256-long k chunks, then
+//     INT32, for BF16).
+//  4. acc = sum_d P_d 2^(-b d) in FP64 (increasing d);
+//     C = alpha * 2^(E_i+F_j) acc + beta * C.
+// The workspace holds E, F and the slices, padded to 128 in every extent
+// with zeros so that the product kernel runs without bounds checks.
+#include "split.h"
+
+#include <algorithm>
+#include <climits>
+
+#include "gemm_native.h"
+
+namespace mg {
+
+namespace {
+
+constexpr int kStageBytes = 128;  // k bytes of one slice row per LDS stage
+constexpr int kPitch = kStageBytes + 16;  // LDS row pitch: conflict-free b128 reads
+
+__device__ __forceinline__ int exp_of(double x) {
+  if (x == 0.0) return INT_MIN;
+  int e;
+  (void)frexp(x, &e);
+  return e;
+}
+
+// ------------------------------------------------------------ step 1: scales
+__global__ void row_exp_kernel(const double *A, int64_t lda, int m, int k, int mp, int *E) {
+  const int row = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= mp) return;  // uniform per wave
+  int e = INT_MIN;
+  if (row < m) {
+    const double *p = A + (int64_t)row * lda;
+    for (int c = lane; c < k; c += 64) e = max(e, exp_of(p[c]));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) e = max(e, __shfl_xor(e, off));
+  if (lane == 0) E[row] = (e == INT_MIN) ? 0 : e;
+}
+
+__global__ void fill_int_kernel(int *p, int count, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+constexpr int kColRows = 256;  // rows of B per thread in col_exp_kernel
+
+__global__ void col_exp_kernel(const double *B, int64_t ldb, int k, int n, int *F) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int nchunks = (k + kColRows - 1) / kColRows;
+  for (int ch = blockIdx.y; ch < nchunks; ch += gridDim.y) {
+    int e = INT_MIN;
+    const int r1 = min(k, (ch + 1) * kColRows);
+    for (int r = ch * kColRows; r < r1; ++r) e = max(e, exp_of(B[(int64_t)r * ldb + j]));
+    if (e != INT_MIN) atomicMax(F + j, e);
+  }
+}
+
+__global__ void col_exp_finish_kernel(int *F, int n, int np) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < np && (j >= n || F[j] == INT_MIN)) F[j] = 0;
+}
+
+// ------------------------------------------------------------ step 2: slices
+// Packs CW slice values (CW*ESZ == 16 bytes) into one 16-byte store.
+template <int ESZ>
+struct SlicePack;
+
+template <>
+struct SlicePack<1> {  // INT8
+  static constexpr int CW = 16;
+  __device__ static __forceinline__ i4v pack(const int *q) {
+    i4v o;
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+      o[w] = (q[4 * w] & 0xff) | ((q[4 * w + 1] & 0xff) << 8) | ((q[4 * w + 2] & 0xff) << 16) |
+             ((q[4 * w + 3] & 0xff) << 24);
+    return o;
+  }
+};
+
+template <>
+struct SlicePack<2> {  // BF16: an integer |q| <= 256 is exact in bf16 = top half of its float
+  static constexpr int CW = 8;
+  __device__ static __forceinline__ unsigned bf16_bits(int q) {
+    return __float_as_uint((float)q) >> 16;
+  }
+  __device__ static __forceinline__ i4v pack(const int *q) {
+    i4v o;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) o[w] = (int)(bf16_bits(q[2 * w]) | (bf16_bits(q[2 * w + 1]) << 16));
+    return o;
+  }
+};
+
+// One slicing round on CW values: y = r*2^b, q = trunc(y), r = y - q.
+template <int CW>
+__device__ __forceinline__ void slice_round(double *r, int *q, int bits) {
+#pragma unroll
+  for (int e = 0; e < CW; ++e) {
+    const double y = ldexp(r[e], bits);
+    const double t = trunc(y);
+    q[e] = (int)t;
+    r[e] = y - t;
+  }
+}
+
+// A slices, row-major [s][mp][kp]: one thread per (row, 16-byte chunk).
+template <int ESZ>
+__global__ void slice_rows_kernel(const double *A, int64_t lda, int m, int k, int mp, int64_t kp,
+                                  const int *E, int s, int bits, unsigned char *out) {
+  constexpr int CW = SlicePack<ESZ>::CW;
+  const int64_t chunks_per_row = kp / CW;
+  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (id >= (int64_t)mp * chunks_per_row) return;
+  const int i = (int)(id / chunks_per_row);
+  const int64_t c0 = (id % chunks_per_row) * CW;
+  const int ei = E[i];
+  double r[CW];
+#pragma unroll
+  for (int e = 0; e < CW; ++e) {
+    const int64_t kk = c0 + e;
+    const double x = (i < m && kk < k) ? A[(int64_t)i * lda + kk] : 0.0;
+    r[e] = ldexp(x, -ei);
+  }
+  const int64_t slice_bytes = (int64_t)mp * kp * ESZ;
+  unsigned char *o = out + ((int64_t)i * kp + c0) * ESZ;
+  for (int t = 0; t < s; ++t) {
+    int q[CW];
+    slice_round<CW>(r, q, bits);
+    *reinterpret_cast<i4v *>(o + t * slice_bytes) = SlicePack<ESZ>::pack(q);
+  }
+}
+
+// B slices, stored transposed [s][np][kp] (k contiguous per column of B):
+// a 64 x 64 block of B is transposed through LDS.
+template <int ESZ>
+__global__ __launch_bounds__(256) void slice_cols_kernel(const double *B, int64_t ldb, int k, int n,
+                                                         int np, int64_t kp, const int *F, int s,
+                                                         int bits, unsigned char *out) {
+  __shared__ double T[64][65];
+  const int64_t kblocks = kp / 64;
+  const int j0 = (int)(blockIdx.x / kblocks) * 64;
+  const int64_t k0 = (blockIdx.x % kblocks) * 64;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int kk = e >> 6, jj = e & 63;
+    const int64_t gk = k0 + kk;
+    const int gj = j0 + jj;
+    T[kk][jj] = (gk < k && gj < n) ? B[gk * ldb + gj] : 0.0;
+  }
+  __syncthreads();
+  const int jj = tid & 63, kq = tid >> 6;  // column, 16-long k range
+  const int j = j0 + jj;
+  const int fj = F[j];
+  double r[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) r[e] = ldexp(T[kq * 16 + e][jj], -fj);
+  constexpr int CW = SlicePack<ESZ>::CW;
+  const int64_t slice_bytes = (int64_t)np * kp * ESZ;
+  unsigned char *o = out + ((int64_t)j * kp + k0 + kq * 16) * ESZ;
+  for (int t = 0; t < s; ++t) {
+    int q[16];
+    slice_round<16>(r, q, bits);
+#pragma unroll
+    for (int h = 0; h < 16 / CW; ++h)
+      *reinterpret_cast<i4v *>(o + t * slice_bytes + h * 16) = SlicePack<ESZ>::pack(q + h * CW);
+  }
+}
+
+// ------------------------------------------------- steps 3-4: slice products
+template <int ALGO>
+struct SplitMma;
+
+template <>
+struct SplitMma<MG_SPLIT_I8> {
+  typedef i4v acc_t;
+  static constexpr int ESZ = 1;
+  static constexpr int CHUNK_STAGES = 0;  // INT32 accumulates the diagonal directly
+  __device__ static __forceinline__ acc_t mma(i4v a, i4v b, acc_t c) {
+    return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
+  }
+};
+
+template <>
+struct SplitMma<MG_SPLIT_BF16> {
+  typedef f4v acc_t;
+  static constexpr int ESZ = 2;
+  static constexpr int CHUNK_STAGES = 4;  // 256 k: 256 * 255^2 < 2^24 keeps FP32 exact
+  __device__ static __forceinline__ acc_t mma(i4v a, i4v b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, a),
+                                                   __builtin_bit_cast(bf8v, b), c, 0, 0, 0);
+  }
+};
+
+struct SplitArgs {
+  const unsigned char *As, *Bs;
+  const int *E, *F;
+  double *C;
+  int64_t ldc;
+  int m, n, mp, np;
+  int64_t kp_bytes;  // row pitch of a slice in bytes
+  int s, bits;
+  int seg_stages, total_stages;
+  double alpha, beta;
+};
+
+struct Step {
+  int seg, d, p, st;
+};
+
+__device__ __forceinline__ int pmax_of(int d, int s) { return min(s, d - 1); }
+
+__device__ __forceinline__ int seg_len(int seg, const SplitArgs &a) {
+  return min(a.seg_stages, a.total_stages - seg * a.seg_stages);
+}
+
+// Next (segment, diagonal, pair, stage) in the order the kernel walks them.
+__device__ __forceinline__ void advance(Step &x, const SplitArgs &a) {
+  if (++x.st < seg_len(x.seg, a)) return;
+  x.st = 0;
+  if (++x.p <= pmax_of(x.d, a.s)) return;
+  if (++x.d > a.s + 1) {
+    x.d = 2;
+    ++x.seg;
+  }
+  x.p = max(1, x.d - a.s);
+}
+
+constexpr int kSBM = 128, kSBN = 128;
+
+template <int ALGO>
+__global__ __launch_bounds__(256, 1) void split_gemm_kernel(SplitArgs a, int tiles_m, int tiles_n) {
+  typedef SplitMma<ALGO> M;
+  typedef typename M::acc_t Acc;
+  extern __shared__ __align__(16) unsigned char lds[];
+  constexpr int STAGE = (kSBM + kSBN) * kPitch;
+
+  int tm, tn;
+  grouped_tile(xcd_remap(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, tm, tn);
+  const int m0 = tm * kSBM, n0 = tn * kSBN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
+  const int g = lane >> 4, l16 = lane & 15;
+
+  const int64_t a_slice = (int64_t)a.mp * a.kp_bytes, b_slice = (int64_t)a.np * a.kp_bytes;
+  // 16-byte chunk q = tid + 256u of a 128-row x 128-byte stage: row q/8, byte (q%8)*16.
+  int lrow[4], lcol[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int q = tid + 256 * u;
+    lrow[u] = q >> 3;
+    lcol[u] = (q & 7) * 16;
+  }
+  const unsigned char *abase = a.As + (int64_t)m0 * a.kp_bytes;
+  const unsigned char *bbase = a.Bs + (int64_t)n0 * a.kp_bytes;
+
+  i4v ra[4], rb[4];
+  auto load = [&](const Step &x) {
+    const int64_t koff = (int64_t)(x.seg * a.seg_stages + x.st) * kStageBytes;
+    const unsigned char *pa = abase + (x.p - 1) * a_slice + koff;
+    const unsigned char *pb = bbase + (x.d - x.p - 1) * b_slice + koff;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ra[u] = *reinterpret_cast<const i4v *>(pa + lrow[u] * a.kp_bytes + lcol[u]);
+      rb[u] = *reinterpret_cast<const i4v *>(pb + lrow[u] * a.kp_bytes + lcol[u]);
+    }
+  };
+  auto store = [&](int stage) {
+    unsigned char *As = lds + stage * STAGE;
+    unsigned char *Bs = As + kSBM * kPitch;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      *reinterpret_cast<i4v *>(As + lrow[u] * kPitch + lcol[u]) = ra[u];
+      *reinterpret_cast<i4v *>(Bs + lrow[u] * kPitch + lcol[u]) = rb[u];
+    }
+  };
+
+  Acc acc[4][4];
+  i4v dacc[4][4];  // BF16 only: exact INT32 diagonal sum of FP32 chunk results
+  double facc[4][4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc[i][j] = Acc{};
+      dacc[i][j] = i4v{};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) facc[i][j][r] = 0.0;
+    }
+
+  const int pairs = a.s * (a.s + 1) / 2;
+  const int T = pairs * a.total_stages;
+  Step cur = {0, 2, 1, 0};
+  load(cur);
+  store(0);
+  __syncthreads();
+  for (int t = 0; t < T; ++t) {
+    Step nxt = cur;
+    advance(nxt, a);
+    if (t + 1 < T) load(nxt);
+    const unsigned char *As = lds + (t & 1) * STAGE;
+    const unsigned char *Bs = As + kSBM * kPitch;
+#pragma unroll
+    for (int h = 0; h < kStageBytes / 64; ++h) {
+      i4v fa[4], fb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        fa[i] = *reinterpret_cast<const i4v *>(As + (wm0 + 16 * i + l16) * kPitch + h * 64 + g * 16);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        fb[j] = *reinterpret_cast<const i4v *>(Bs + (wn0 + 16 * j + l16) * kPitch + h * 64 + g * 16);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = M::mma(fa[i], fb[j], acc[i][j]);
+    }
+    const bool seg_last = cur.st + 1 == seg_len(cur.seg, a);
+    if (M::CHUNK_STAGES > 0 && ((cur.st + 1) % (M::CHUNK_STAGES > 0 ? M::CHUNK_STAGES : 1) == 0 ||
+                                seg_last)) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            dacc[i][j][r] += (int)acc[i][j][r];
+            acc[i][j][r] = 0;
+          }
+    }
+    if (seg_last && cur.p == pmax_of(cur.d, a.s)) {
+      const double sc = ldexp(1.0, -a.bits * cur.d);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int v = M::CHUNK_STAGES > 0 ? dacc[i][j][r] : (int)acc[i][j][r];
+            facc[i][j][r] = fma((double)v, sc, facc[i][j][r]);
+            dacc[i][j][r] = 0;
+            if (M::CHUNK_STAGES == 0) acc[i][j][r] = 0;
+          }
+    }
+    if (t + 1 < T) store((t + 1) & 1);
+    __syncthreads();
+    cur = nxt;
+  }
+
+  // Epilogue: C = alpha * 2^(E_i + F_j) * acc + beta * C, rounded as written.
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = n0 + wn0 + 16 * j + l16;
+      if (col >= a.n) continue;
+      const int fj = a.F[col];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm0 + 16 * i + 4 * g + r;
+        if (row >= a.m) continue;
+        const double prod = ldexp(facc[i][j][r], a.E[row] + fj);
+        double *pc = a.C + (int64_t)row * a.ldc + col;
+        double o = __dmul_rn(a.alpha, prod);
+        if (a.beta != 0.0) o = __dadd_rn(o, __dmul_rn(a.beta, *pc));
+        *pc = o;
+      }
+    }
+}
+
+template <typename K>
+int ensure_lds(K kern, size_t bytes) {
+  MG_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  return MG_OK;
+}
+
+}  // namespace
+
+int split_default_slices(int algo) { return algo == MG_SPLIT_BF16 ? 6 : 7; }
+
+int split_bits(int algo) { return algo == MG_SPLIT_BF16 ? 8 : 7; }
+
+int split_layout(int algo, int slices, int64_t m, int64_t n, int64_t k, SplitLayout *L) {
+  if (algo != MG_SPLIT_I8 && algo != MG_SPLIT_BF16) {
+    set_error("not a split algorithm: %d", algo);
+    return MG_ERR_INVALID_ARG;
+  }
+  if (slices < 1 || slices > kSplitMaxSlices) {
+    set_error("slices must be in [1, %d], got %d", kSplitMaxSlices, slices);
+    return MG_ERR_INVALID_ARG;
+  }
+  if (m < 0 || n < 0 || k < 0) {
+    set_error("negative extent");
+    return MG_ERR_INVALID_ARG;
+  }
+  L->mp = round_up(std::max<int64_t>(m, 1), kSplitTile);
+  L->np = round_up(std::max<int64_t>(n, 1), kSplitTile);
+  L->kp = round_up(std::max<int64_t>(k, 1), kSplitTile);
+  L->elem_bytes = algo == MG_SPLIT_BF16 ? 2 : 1;
+  int64_t off = 0;
+  L->e_off = off;
+  off = round_up(off + 4 * L->mp, 256);
+  L->f_off = off;
+  off = round_up(off + 4 * L->np, 256);
+  L->a_off = off;
+  off = round_up(off + slices * L->mp * L->kp * L->elem_bytes, 256);
+  L->b_off = off;
+  off = round_up(off + slices * L->np * L->kp * L->elem_bytes, 256);
+  L->total = off;
+  return MG_OK;
+}
+
+int split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, const double *A,
+                  int64_t lda, const double *B, int64_t ldb, void *ws, hipStream_t s) {
+  SplitLayout L;
+  int rc = split_layout(algo, slices, m, n, k, &L);
+  if (rc != MG_OK) return rc;
+  unsigned char *w = static_cast<unsigned char *>(ws);
+  int *E = reinterpret_cast<int *>(w + L.e_off);
+  int *F = reinterpret_cast<int *>(w + L.f_off);
+  const int bits = split_bits(algo);
+  const int mp = (int)L.mp, np = (int)L.np;
+
+  hipLaunchKernelGGL(row_exp_kernel, dim3((unsigned)ceil_div(mp, 4)), dim3(256), 0, s, A, lda,
+                     (int)m, (int)k, mp, E);
+  hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)ceil_div(np, 256)), dim3(256), 0, s, F, np,
+                     INT_MIN);
+  if (n > 0 && k > 0) {
+    const int64_t nchunks = ceil_div(k, kColRows);
+    hipLaunchKernelGGL(col_exp_kernel,
+                       dim3((unsigned)ceil_div(n, 256), (unsigned)std::min<int64_t>(nchunks, 4096)),
+                       dim3(256), 0, s, B, ldb, (int)k, (int)n, F);
+  }
+  hipLaunchKernelGGL(col_exp_finish_kernel, dim3((unsigned)ceil_div(np, 256)), dim3(256), 0, s, F,
+                     (int)n, np);
+  MG_HIP_TRY(hipGetLastError());
+
+  unsigned char *As = w + L.a_off, *Bs = w + L.b_off;
+  const int64_t cw = algo == MG_SPLIT_BF16 ? 8 : 16;
+  const int64_t rthreads = L.mp * (L.kp / cw);
+  const int64_t cblocks = (L.np / 64) * (L.kp / 64);
+  if (rthreads / 256 + 1 > INT32_MAX || cblocks > INT32_MAX) {
+    set_error("split operands too large");
+    return MG_ERR_INVALID_ARG;
+  }
+  if (algo == MG_SPLIT_BF16) {
+    hipLaunchKernelGGL(slice_rows_kernel<2>, dim3((unsigned)ceil_div(rthreads, 256)), dim3(256), 0,
+                       s, A, lda, (int)m, (int)k, mp, L.kp, E, slices, bits, As);
+    hipLaunchKernelGGL(slice_cols_kernel<2>, dim3((unsigned)cblocks), dim3(256), 0, s, B, ldb,
+                       (int)k, (int)n, np, L.kp, F, slices, bits, Bs);
+  } else {
+    hipLaunchKernelGGL(slice_rows_kernel<1>, dim3((unsigned)ceil_div(rthreads, 256)), dim3(256), 0,
+                       s, A, lda, (int)m, (int)k, mp, L.kp, E, slices, bits, As);
+    hipLaunchKernelGGL(slice_cols_kernel<1>, dim3((unsigned)cblocks), dim3(256), 0, s, B, ldb,
+                       (int)k, (int)n, np, L.kp, F, slices, bits, Bs);
+  }
+  MG_HIP_TRY(hipGetLastError());
+  return MG_OK;
+}
+
+int split_multiply(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
+                   double beta, double *C, int64_t ldc, const void *ws, hipStream_t s) {
+  SplitLayout L;
+  int rc = split_layout(algo, slices, m, n, k, &L);
+  if (rc != MG_OK) return rc;
+  const unsigned char *w = static_cast<const unsigned char *>(ws);
+  SplitArgs a;
+  a.As = w + L.a_off;
+  a.Bs = w + L.b_off;
+  a.E = reinterpret_cast<const int *>(w + L.e_off);
+  a.F = reinterpret_cast<const int *>(w + L.f_off);
+  a.C = C;
+  a.ldc = ldc;
+  a.m = (int)m;
+  a.n = (int)n;
+  a.mp = (int)L.mp;
+  a.np = (int)L.np;
+  a.kp_bytes = L.kp * L.elem_bytes;
+  a.s = slices;
+  a.bits = split_bits(algo);
+  a.total_stages = (int)(a.kp_bytes / kStageBytes);
+  // Longest k segment whose diagonal sums stay exact in INT32:
+  // slices * kseg * (2^b - 1)^2 < 2^31.
+  const int64_t smax = (int64_t)((1u << a.bits) - 1) * ((1u << a.bits) - 1);
+  const int64_t kseg = ((int64_t)INT32_MAX / (slices * smax));
+  const int64_t per_stage = kStageBytes / L.elem_bytes;
+  int64_t seg_stages = kseg / per_stage;
+  if (algo == MG_SPLIT_BF16) seg_stages -= seg_stages % SplitMma<MG_SPLIT_BF16>::CHUNK_STAGES;
+  if (seg_stages < 1) {
+    set_error("too many slices for exact INT32 accumulation");
+    return MG_ERR_INVALID_ARG;
+  }
+  a.seg_stages = (int)std::min<int64_t>(seg_stages, a.total_stages);
+  a.alpha = alpha;
+  a.beta = beta;
+  const int tiles_m = (int)(L.mp / kSBM), tiles_n = (int)(L.np / kSBN);
+  const size_t lds = 2 * (size_t)(kSBM + kSBN) * kPitch;
+  if (algo == MG_SPLIT_BF16) {
+    static int once = ensure_lds(split_gemm_kernel<MG_SPLIT_BF16>, lds);
+    if (once != MG_OK) return once;
+    hipLaunchKernelGGL(split_gemm_kernel<MG_SPLIT_BF16>, dim3(tiles_m * tiles_n), dim3(256), lds, s,
+                       a, tiles_m, tiles_n);
+  } else {
+    static int once = ensure_lds(split_gemm_kernel<MG_SPLIT_I8>, lds);
+    if (once != MG_OK) return once;
+    hipLaunchKernelGGL(split_gemm_kernel<MG_SPLIT_I8>, dim3(tiles_m * tiles_n), dim3(256), lds, s,
+                       a, tiles_m, tiles_n);
+  }
+  MG_HIP_TRY(hipGetLastError());
+  return MG_OK;
+}
+
+int gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
+               const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+               double *C, int64_t ldc, void *ws, int64_t ws_bytes, hipStream_t s) {
+  if (m == 0 || n == 0) return MG_OK;
+  SplitLayout L;
+  int rc = split_layout(algo, slices, m, n, k, &L);
+  if (rc != MG_OK) return rc;
+  if (alpha == 0.0 || k == 0)  // C <- beta*C: A and B are not read
+    return gemm_native(MG_F64, 0, m, n, 0, 0.0, nullptr, 1, nullptr, 1, beta, C, ldc, s);
+  if (ws == nullptr || ws_bytes < L.total) {
+    set_error("split workspace too small: need %lld bytes", (long long)L.total);
+    return MG_ERR_INVALID_ARG;
+  }
+  rc = split_prepare(algo, slices, m, n, k, A, lda, B, ldb, ws, s);
+  if (rc != MG_OK) return rc;
+  return split_multiply(algo, slices, m, n, k, alpha, beta, C, ldc, ws, s);
+}
+
+int gemm_split_pooled(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
+                      const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+                      double *C, int64_t ldc, hipStream_t s) {
+  if (m == 0 || n == 0) return MG_OK;
+  SplitLayout L;
+  int rc = split_layout(algo, slices, m, n, k, &L);
+  if (rc != MG_OK) return rc;
+  if (alpha == 0.0 || k == 0)
+    return gemm_split(algo, slices, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, 0, s);
+  void *ws = nullptr;
+  hipError_t e = hipMallocAsync(&ws, (size_t)L.total, s);
+  if (e != hipSuccess) {
+    set_error("hipMallocAsync(%lld bytes) failed: %s", (long long)L.total, hipGetErrorString(e));
+    return MG_ERR_NO_MEMORY;
+  }
+  rc = gemm_split(algo, slices, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ws, L.total, s);
+  MG_HIP_TRY(hipFreeAsync(ws, s));
+  return rc;
+}
+
+}  // namespace mg

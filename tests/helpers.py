@@ -1,0 +1,49 @@
+"""Shared test helpers: seeded inputs on host and device, error bounds."""
+
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+import synth
+
+U64 = 2.0 ** -53  # unit roundoff of FP64
+U32 = 2.0 ** -24
+
+
+def host_mats(seed, m, n, k, kind="pm1"):
+    A = synth.matrix(seed, synth.STREAM_A, m, k, kind=kind)
+    B = synth.matrix(seed, synth.STREAM_B, k, n, kind=kind)
+    C = synth.matrix(seed, synth.STREAM_C, m, n)
+    return A, B, C
+
+
+def to_dev(x, dtype=None, ld=None, fill=np.nan):
+    """Host array -> CUDA tensor; with ``ld`` the rows are padded to ``ld``
+    columns and the padding filled with ``fill`` (a view of the first cols
+    is returned, keeping the padded parent alive through .base)."""
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    t = t.cuda()
+    if ld is None or ld == x.shape[1]:
+        return t
+    big = torch.full((x.shape[0], ld), fill, dtype=t.dtype, device=t.device)
+    big[:, : x.shape[1]] = t
+    return big[:, : x.shape[1]]
+
+
+def elementwise_bound(alpha, A, B, beta, C, k, u=U64):
+    """Worst-case bound on |computed - exact| for any summation order with
+    fused or unfused multiply-adds: (k + 2) u (|alpha| |A||B| + |beta||C|),
+    plus a few ulps of the result."""
+    absAB = np.abs(A) @ np.abs(B) if k > 0 else np.zeros((A.shape[0], B.shape[1]))
+    mag = abs(alpha) * absAB + (abs(beta) * np.abs(C) if beta != 0 else 0.0)
+    return (k + 2) * u * mag + 4 * u * np.abs(mag) + 1e-300
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()

@@ -182,6 +182,121 @@ def bench_split(n, steps, warmup):
     return out
 
 
+def batched_roofline_ms(shapes, esz, peak_tflops):
+    """Sum over problems of max(FLOP / peak, compulsory bytes / 8 TB/s), ms."""
+    m, n, k = (shapes[:, i].astype(np.float64) for i in range(3))
+    flop = 2 * m * n * k
+    byts = esz * (m * k + k * n + 2 * m * n)
+    return float(np.sum(np.maximum(flop / (peak_tflops * 1e12), byts / 8e12)) * 1e3), \
+        float(flop.sum()), float(byts.sum())
+
+
+def bench_batched(steps):
+    """2000 problems, m, n, k log-uniform in [16, 512], FP64 and FP32: one
+    persistent launch per batch, graph-replayed, tile classes autotuned."""
+    import torch
+    import paper_1602_08477_amd as mg
+    import synth
+    seed = synth.config_seed(4)
+    shapes = synth.batch_shapes(seed, 2000)
+    out = {}
+    for name, dt, code, peak in (("f64", torch.float64, mg.F64, FP64_PEAK),
+                                 ("f32", torch.float32, mg.F32, 157.3)):
+        esz = 8 if dt == torch.float64 else 4
+        offs = {"A": [0], "B": [0], "C": [0]}
+        for m_, n_, k_ in shapes:
+            for key, sz in (("A", m_ * k_), ("B", k_ * n_), ("C", m_ * n_)):
+                offs[key].append(offs[key][-1] + -(-int(sz) // 32) * 32)
+        flats = {key: synth.flat_uniform(seed, i, offs[key][-1], device="cuda").to(dt)
+                 for i, key in enumerate(("A", "B", "C"))}
+        probs = []
+        for i, (m_, n_, k_) in enumerate(shapes):
+            m_, n_, k_ = int(m_), int(n_), int(k_)
+            A = flats["A"][offs["A"][i]: offs["A"][i] + m_ * k_].view(m_, k_)
+            B = flats["B"][offs["B"][i]: offs["B"][i] + k_ * n_].view(k_, n_)
+            C = flats["C"][offs["C"][i]: offs["C"][i] + m_ * n_].view(m_, n_)
+            probs.append(mg.problem(A, B, C, 1.0, 1.0))
+        t0 = time.perf_counter()
+        table = mg.autotune(code, reps=2)
+        tune_s = time.perf_counter() - t0
+        plan = mg.Plan(code, probs, table)
+        plan_h = mg.Plan(code, probs)  # heuristic table, for comparison
+        stream = torch.cuda.current_stream()
+        per_g, _ = time_launches(lambda: plan.launch(graph=True), steps, 3, stream)
+        per_d, _ = time_launches(lambda: plan.launch(graph=False), steps, 3, stream)
+        per_h, _ = time_launches(lambda: plan_h.launch(graph=True), steps, 3, stream)
+        ms = float(np.median(per_g))
+        roof_ms, flop, byts = batched_roofline_ms(shapes, esz, peak)
+        st = plan.stats()
+        out[name] = {"problems": 2000, "ms": round(ms, 4), "tflops": round(flop / ms / 1e9, 2),
+                     "roofline_ms": round(roof_ms, 4), "roofline_frac": round(roof_ms / ms, 4),
+                     "ms_direct_launch": round(float(np.median(per_d)), 4),
+                     "ms_heuristic_table": round(float(np.median(per_h)), 4),
+                     "tiles": st["tiles"], "workgroups": st["workgroups"],
+                     "tiles_per_class": st["tiles_per_class"], "autotune_s": round(tune_s, 2),
+                     "gflop": round(flop / 1e9, 3), "gbytes": round(byts / 1e9, 3)}
+        plan.close()
+        plan_h.close()
+        del flats, probs
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_serving(seconds, rate=2000.0):
+    """Open-loop Poisson arrivals, square n log-uniform in [32, 2048], 70 %
+    native FP64 / 30 % split-INT8, operands resident on the device, HBM cap
+    64 GiB; latency from each request's scheduled arrival to completion."""
+    import torch
+    import paper_1602_08477_amd as mg
+    import synth
+    seed = synth.config_seed(5)
+    count = int(rate * seconds)
+    gaps = synth.poisson_gaps(seed, synth.STREAM_ARRIVALS, count, rate)
+    t_arr = np.cumsum(gaps) - gaps[0]
+    ns = synth.log_uniform_int(seed, synth.STREAM_SIZES, count, 32, 2048)
+    mix = synth.uniform_unit(seed, synth.STREAM_MIX, count)
+    algos = np.where(mix < 0.3, mg.SPLIT_I8, mg.NATIVE)
+    nmax = 2048
+    pool_elems = 1 << 26  # 512 MiB of U[-1,1) operands, requests read views of it
+    pool_a = synth.flat_uniform(seed, 0, pool_elems, device="cuda")
+    pool_b = synth.flat_uniform(seed, 1, pool_elems, device="cuda")
+    ring = 256
+    cbuf = torch.zeros(ring, nmax * nmax, dtype=torch.float64, device="cuda")
+    offs = synth.log_uniform_int(seed, 12, count, 1, pool_elems - nmax * nmax - 1) // 32 * 32
+    reqs = (mg.Request * count)()
+    base_a, base_b, base_c = pool_a.data_ptr(), pool_b.data_ptr(), cbuf.data_ptr()
+    for i in range(count):
+        n = int(ns[i])
+        o = int(offs[i]) * 8
+        reqs[i] = mg.Request(mg.F64, int(algos[i]),
+                             mg.Problem(n, n, n, 1.0, 1.0, base_a + o, n, base_b + o, n,
+                                        base_c + (i % ring) * nmax * nmax * 8, n),
+                             int(t_arr[i] * 1e9))
+    table = mg.autotune(mg.F64, reps=2)
+    with mg.Server(n_streams=4, max_slots=ring, max_batch=64, hbm_budget_bytes=64 << 30,
+                   table=table) as srv:
+        res = srv.replay(reqs)
+        st = srv.stats()
+    ok = np.array([r.status == 0 for r in res])
+    lat = np.array([(r.t_done_ns - r.t_arrival_ns) / 1e6 for r in res])[ok]
+    t0 = min(r.t_arrival_ns for r in res)
+    t1 = max(r.t_done_ns for r in res if r.status == 0)
+    flop = float(np.sum(2.0 * ns.astype(np.float64) ** 3 * ok))
+    bsz = np.array([r.batch_size for r in res])[ok]
+    del cbuf, pool_a, pool_b
+    torch.cuda.empty_cache()
+    return {"requests": count, "rate_per_s": rate, "seconds": seconds,
+            "completed_ok": int(ok.sum()), "rejected_or_failed": int((~ok).sum()),
+            "p50_ms": round(float(np.percentile(lat, 50)), 4),
+            "p99_ms": round(float(np.percentile(lat, 99)), 4),
+            "p999_ms": round(float(np.percentile(lat, 99.9)), 4),
+            "mean_ms": round(float(lat.mean()), 4),
+            "delivered_tflops": round(flop / ((t1 - t0) / 1e9) / 1e12, 3),
+            "mean_batch_size": round(float(bsz.mean()), 2), "batches": st["batches"],
+            "max_batch": st["max_batch_seen"], "max_inflight_gib": round(
+                st["max_inflight_bytes"] / 2 ** 30, 3)}
+
+
 def cpu_baseline(n, target_s=12.0):
     """The oracle on this host: output rows of the n=8192 workload, doubling
     the row count until one run takes at least ``target_s`` / 4 seconds, then
@@ -214,6 +329,7 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--quick", action="store_true", help="headline only (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the GEMM path "
@@ -260,6 +376,11 @@ def main():
     if not args.quick:
         eprint("bench: split precision n=4096")
         rec["split"] = bench_split(4096, max(5, args.steps), 2)
+        eprint("bench: batched 2000 problems")
+        rec["batched"] = bench_batched(max(10, args.steps))
+        if args.serve_seconds > 0:
+            eprint(f"bench: serving {args.serve_seconds:.0f} s")
+            rec["serving"] = bench_serving(args.serve_seconds)
         if not args.no_cpu_baseline:
             eprint("bench: cpu baseline (oracle)")
             rec["cpu_baseline"] = cpu_baseline(n)

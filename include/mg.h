@@ -146,6 +146,159 @@ int mg_gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double 
                   double *C, int64_t ldc, void *workspace, int64_t workspace_bytes,
                   void *stream);
 
+/* ------------------------------------------------------- batched GEMM --
+ * Many independent problems C_i <- alpha_i A_i B_i + beta_i C_i (each the
+ * Section 4.2 operation) in ONE persistent launch.  A plan validates the
+ * problems, picks a tile class per problem (from a tuning table or a
+ * heuristic), builds a device work list of macro-tiles sorted longest first,
+ * and on first launch captures [counter reset, persistent kernel] in a HIP
+ * graph that later launches replay.  The grid is (CUs x occupancy)
+ * workgroups; each pulls tiles through an atomic counter (blocks are
+ * otherwise independent, Section 3.2), so a problem's result is the same
+ * whatever else is in the batch.
+ * Problems may share A and B; no C may overlap another problem's C, A or B
+ * (checked on the byte spans [first element, last element], so interleaved
+ * sub-blocks of one buffer are rejected).  dtype MG_F64 or MG_F32. */
+typedef struct mg_problem {
+  int64_t m, n, k;
+  double alpha, beta;
+  const void *A;
+  int64_t lda;
+  const void *B;
+  int64_t ldb;
+  void *C;
+  int64_t ldc;
+} mg_problem;
+
+#define MG_NUM_GROUPED_CLASSES 3 /* tile classes: 128x64, 64x64, 32x32   */
+#define MG_TUNE_EDGES 6          /* per-extent buckets, see mg_tune_bucket */
+#define MG_TUNE_BUCKETS 216      /* MG_TUNE_EDGES^3                        */
+
+/* Tile class per shape bucket.  Bucket of an extent x: 0 for x < 32, b for
+ * 16*2^b <= x < 32*2^b (b = 1..4), 5 for x >= 512; the table index is
+ * (bucket(m)*6 + bucket(n))*6 + bucket(k). */
+typedef struct mg_tune_table {
+  int32_t dtype;
+  int32_t cls[MG_TUNE_BUCKETS];
+} mg_tune_table;
+
+typedef struct mg_plan_stats {
+  int64_t problems, tiles, workgroups, occupancy;
+  int64_t tiles_per_class[MG_NUM_GROUPED_CLASSES];
+  int64_t scale_tiles; /* tiles of problems with alpha == 0 or k == 0        */
+  double flops;        /* sum of 2mnk                                        */
+  double bytes;        /* sum of compulsory operand bytes                    */
+  int64_t graph;       /* 1 once the launch has been captured in a graph     */
+} mg_plan_stats;
+
+typedef struct mg_plan mg_plan;
+
+/* Macro-tile of tile class `cls`. */
+int mg_grouped_class_info(int cls, int *bm, int *bn);
+/* Index of (m, n, k) in mg_tune_table.cls. */
+int mg_tune_bucket(int64_t m, int64_t n, int64_t k);
+/* Heuristic table (largest tile wasting at most a quarter of its area). */
+int mg_tune_default(int dtype, mg_tune_table *out);
+/* Autotuner: for every bucket, times each tile class on a batch of 48
+ * problems of the bucket's representative shape (reps launches on `stream`,
+ * HIP events) and records the fastest.  Allocates and frees its own scratch
+ * operands; blocks until done. */
+int mg_autotune(int dtype, int reps, void *stream, mg_tune_table *out);
+
+/* Builds a plan (host work list + device copy; blocks while uploading).
+ * `table` may be NULL (heuristic).  *out must be released with
+ * mg_plan_destroy.  Errors: MG_ERR_INVALID_ARG naming the first bad problem
+ * index, MG_ERR_HIP on allocation/copy failure. */
+int mg_plan_create(int dtype, int64_t count, const mg_problem *probs,
+                   const mg_tune_table *table, mg_plan **out);
+/* Enqueues the whole batch on `stream` by replaying the plan's graph
+ * (captured on first use). */
+int mg_plan_launch(mg_plan *plan, void *stream);
+/* The same two kernels launched directly (no graph). */
+int mg_plan_launch_direct(mg_plan *plan, void *stream);
+int mg_plan_get_stats(const mg_plan *plan, mg_plan_stats *out);
+/* Frees the plan.  The caller must make sure no launch of it is pending. */
+int mg_plan_destroy(mg_plan *plan);
+
+/* One-shot: plan (heuristic table) + direct launch on `stream`.  The plan's
+ * device memory is released by a later library call once an event recorded
+ * after the launch has completed.  algo must be MG_NATIVE. */
+int mg_gemm_batched(int dtype, int algo, int64_t count, const mg_problem *probs, void *stream);
+
+/* ----------------------------------------------------------- serving --
+ * A request loop with continuous batching.  Requests (each one GEMM of the
+ * Section 4.2 form, operands already on the device) are submitted from any
+ * thread; a scheduler thread admits them in FIFO order while the admitted-
+ * but-unfinished requests stay within `max_slots` and their bytes (A + B + C,
+ * plus the split workspace for split requests) within `hbm_budget_bytes`, and
+ * launches everything admitted so far as one batch on the next free stream
+ * (one persistent grouped launch for the native requests, the split kernels
+ * for split requests).  Batches on different streams run concurrently on the
+ * device (the paper's scheduler may run grids from several streams in
+ * parallel, Section 3.3); requests that arrive while batches run are admitted
+ * as slots and bytes free up and go out with the next batch.  A request's
+ * arithmetic depends only on its own shape (fixed tile class table), so its
+ * result is the same alone or in any mix.
+ * The caller keeps every operand alive and unmodified until the request is
+ * reported done; the library never copies operands.
+ * Timestamps are steady-clock nanoseconds (mg_now_ns). */
+typedef struct mg_server mg_server;
+
+typedef struct mg_server_opts {
+  int n_streams;            /* concurrent batches (1..8)                     */
+  int max_slots;            /* admitted, unfinished requests (>= 1)          */
+  int max_queue;            /* waiting (not admitted) requests (>= 1)        */
+  int max_batch;            /* requests per batch (>= 1)                     */
+  int64_t hbm_budget_bytes; /* admission cap on admitted request bytes       */
+  const mg_tune_table *table; /* tile classes for native requests (NULL:
+                                 heuristic); copied at creation              */
+} mg_server_opts;
+
+typedef struct mg_request {
+  int32_t dtype;          /* MG_F64 or MG_F32                                 */
+  int32_t algo;           /* MG_NATIVE, or MG_SPLIT_I8 / MG_SPLIT_BF16 (F64)  */
+  mg_problem p;
+  int64_t t_arrival_ns;   /* scheduled arrival: latencies are measured from it */
+} mg_request;
+
+typedef struct mg_result {
+  int32_t status;         /* MG_OK or the request's error code               */
+  int32_t batch_size;     /* requests in the batch it ran in                  */
+  int64_t batch_id;
+  int64_t t_arrival_ns, t_submit_ns, t_admit_ns, t_launch_ns, t_done_ns;
+} mg_result;
+
+typedef struct mg_server_stats {
+  int64_t submitted, completed, rejected_busy, rejected_memory, failed;
+  int64_t batches, max_batch_seen, max_inflight_bytes, max_slots_used;
+} mg_server_stats;
+
+/* Steady-clock time in nanoseconds (the server's clock). */
+int64_t mg_now_ns(void);
+
+/* Creates streams, buffers and threads on the calling thread's current
+ * device.  MG_ERR_INVALID_ARG for out-of-range options. */
+int mg_server_create(const mg_server_opts *opts, mg_server **out);
+/* Finishes every submitted request, then releases everything. */
+int mg_server_destroy(mg_server *s);
+/* Non-blocking.  Validates the request (as mg_gemm); MG_ERR_NO_MEMORY if it
+ * alone exceeds the budget, MG_ERR_BUSY if the waiting queue is full;
+ * otherwise queues it and returns its ticket.  t_arrival_ns of 0 means "now". */
+int mg_gemm_submit(mg_server *s, const mg_request *req, uint64_t *ticket);
+/* MG_PENDING while the request runs; once done copies its result, releases
+ * the ticket and returns MG_OK (the request's own status is in out->status).
+ * MG_ERR_NOT_FOUND for an unknown or already released ticket. */
+int mg_gemm_poll(mg_server *s, uint64_t ticket, mg_result *out);
+/* Blocking variant of mg_gemm_poll. */
+int mg_gemm_wait(mg_server *s, uint64_t ticket, mg_result *out);
+int mg_server_get_stats(const mg_server *s, mg_server_stats *out);
+
+/* Open-loop load generator: submits reqs[i] at t0 + reqs[i].t_arrival_ns
+ * (t0 = time of the call; arrival offsets ascending) from a dedicated thread,
+ * then waits for all of them and fills results[i] (absolute timestamps).
+ * A rejected submission is reported in results[i].status. */
+int mg_server_replay(mg_server *s, int64_t count, const mg_request *reqs, mg_result *results);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,6 +76,8 @@ def lib() -> ctypes.CDLL:
                                        _i64, _vp]
         L.mg_gemm_split.argtypes = [_int, _int, _i64, _i64, _i64, _dbl, _vp, _i64, _vp, _i64,
                                     _dbl, _vp, _i64, _vp, _i64, _vp]
+        _bind_batched(L)
+        _bind_server(L)
         _lib = L
     return _lib
 
@@ -204,3 +206,224 @@ def gemm_split(A, B, C, alpha: float = 1.0, beta: float = 0.0, algo: int = SPLIT
                               ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                               _stream_handle(stream)))
     return C
+
+
+# ------------------------------------------------------------ batched GEMM
+NUM_GROUPED_CLASSES = 3
+TUNE_EDGES = 6
+TUNE_BUCKETS = 216
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("m", _i64), ("n", _i64), ("k", _i64), ("alpha", _dbl), ("beta", _dbl),
+                ("A", _vp), ("lda", _i64), ("B", _vp), ("ldb", _i64), ("C", _vp), ("ldc", _i64)]
+
+
+class TuneTable(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("cls", ctypes.c_int32 * TUNE_BUCKETS)]
+
+    def to_list(self):
+        return [int(x) for x in self.cls]
+
+    @classmethod
+    def from_list(cls, dtype, values):
+        t = cls()
+        t.dtype = dtype
+        for i, v in enumerate(values):
+            t.cls[i] = int(v)
+        return t
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [("problems", _i64), ("tiles", _i64), ("workgroups", _i64), ("occupancy", _i64),
+                ("tiles_per_class", _i64 * NUM_GROUPED_CLASSES), ("scale_tiles", _i64),
+                ("flops", _dbl), ("bytes", _dbl), ("graph", _i64)]
+
+
+def _bind_batched(L):
+    L.mg_grouped_class_info.argtypes = [_int, ctypes.POINTER(_int), ctypes.POINTER(_int)]
+    L.mg_tune_bucket.argtypes = [_i64, _i64, _i64]
+    L.mg_tune_default.argtypes = [_int, ctypes.POINTER(TuneTable)]
+    L.mg_autotune.argtypes = [_int, _int, _vp, ctypes.POINTER(TuneTable)]
+    L.mg_plan_create.argtypes = [_int, _i64, ctypes.POINTER(Problem), ctypes.POINTER(TuneTable),
+                                 ctypes.POINTER(_vp)]
+    L.mg_plan_launch.argtypes = [_vp, _vp]
+    L.mg_plan_launch_direct.argtypes = [_vp, _vp]
+    L.mg_plan_get_stats.argtypes = [_vp, ctypes.POINTER(PlanStats)]
+    L.mg_plan_destroy.argtypes = [_vp]
+    L.mg_gemm_batched.argtypes = [_int, _int, _i64, ctypes.POINTER(Problem), _vp]
+
+
+def problem(A, B, C, alpha=1.0, beta=0.0) -> Problem:
+    """Problem descriptor from row-major device tensors (kept alive by the caller)."""
+    (pa, lda), (pb, ldb), (pc, ldc), m, n, k = _mnk(A, B, C, None)
+    return Problem(m, n, k, alpha, beta, pa, lda, pb, ldb, pc, ldc)
+
+
+def _problems(probs):
+    arr = (Problem * max(1, len(probs)))(*probs)
+    return arr, len(probs)
+
+
+def grouped_class_info(cls: int) -> tuple:
+    a, b = _int(), _int()
+    check(lib().mg_grouped_class_info(cls, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def tune_bucket(m: int, n: int, k: int) -> int:
+    return lib().mg_tune_bucket(m, n, k)
+
+
+def tune_default(dtype: int = F64) -> TuneTable:
+    t = TuneTable()
+    check(lib().mg_tune_default(dtype, ctypes.byref(t)))
+    return t
+
+
+def autotune(dtype: int = F64, reps: int = 3, stream=None) -> TuneTable:
+    t = TuneTable()
+    check(lib().mg_autotune(dtype, reps, _stream_handle(stream), ctypes.byref(t)))
+    return t
+
+
+class Plan:
+    """A batch of problems prepared for one persistent (graph-replayed) launch."""
+
+    def __init__(self, dtype, probs, table: TuneTable | None = None, keep=None):
+        arr, n = _problems(probs)
+        h = _vp()
+        check(lib().mg_plan_create(dtype, n, arr, None if table is None else ctypes.byref(table),
+                                   ctypes.byref(h)))
+        self._h = h
+        self._keep = keep  # tensors the plan points into
+
+    def launch(self, stream=None, graph: bool = True):
+        f = lib().mg_plan_launch if graph else lib().mg_plan_launch_direct
+        check(f(self._h, _stream_handle(stream)))
+
+    def stats(self) -> dict:
+        s = PlanStats()
+        check(lib().mg_plan_get_stats(self._h, ctypes.byref(s)))
+        d = {f: getattr(s, f) for f, _ in PlanStats._fields_}
+        d["tiles_per_class"] = list(s.tiles_per_class)
+        return d
+
+    def close(self):
+        if self._h:
+            lib().mg_plan_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gemm_batched(probs, dtype: int = F64, stream=None):
+    """One-shot batched launch (mg_gemm_batched)."""
+    arr, n = _problems(probs)
+    check(lib().mg_gemm_batched(dtype, NATIVE, n, arr, _stream_handle(stream)))
+
+
+# ------------------------------------------------------------------ serving
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("n_streams", _int), ("max_slots", _int), ("max_queue", _int),
+                ("max_batch", _int), ("hbm_budget_bytes", _i64),
+                ("table", ctypes.POINTER(TuneTable))]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("algo", ctypes.c_int32), ("p", Problem),
+                ("t_arrival_ns", _i64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("batch_size", ctypes.c_int32), ("batch_id", _i64),
+                ("t_arrival_ns", _i64), ("t_submit_ns", _i64), ("t_admit_ns", _i64),
+                ("t_launch_ns", _i64), ("t_done_ns", _i64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(f, _i64) for f in ("submitted", "completed", "rejected_busy", "rejected_memory",
+                                    "failed", "batches", "max_batch_seen", "max_inflight_bytes",
+                                    "max_slots_used")]
+
+
+def _bind_server(L):
+    L.mg_now_ns.restype = _i64
+    L.mg_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)]
+    L.mg_server_destroy.argtypes = [_vp]
+    L.mg_gemm_submit.argtypes = [_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    L.mg_gemm_poll.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(Result)]
+    L.mg_gemm_wait.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(Result)]
+    L.mg_server_get_stats.argtypes = [_vp, ctypes.POINTER(ServerStats)]
+    L.mg_server_replay.argtypes = [_vp, _i64, ctypes.POINTER(Request), ctypes.POINTER(Result)]
+
+
+def now_ns() -> int:
+    return lib().mg_now_ns()
+
+
+def result_dict(r: Result) -> dict:
+    return {f: getattr(r, f) for f, _ in Result._fields_}
+
+
+class Server:
+    """Continuous-batching GEMM server (mg_server_*)."""
+
+    def __init__(self, n_streams=4, max_slots=256, max_queue=1 << 20, max_batch=64,
+                 hbm_budget_bytes=64 << 30, table: TuneTable | None = None):
+        self._table = table
+        o = ServerOpts(n_streams, max_slots, max_queue, max_batch, hbm_budget_bytes,
+                       None if table is None else ctypes.pointer(table))
+        h = _vp()
+        check(lib().mg_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, A, B, C, alpha=1.0, beta=0.0, algo=NATIVE, t_arrival_ns=0) -> int:
+        r = Request(_dtype_code(C), algo, problem(A, B, C, alpha, beta), t_arrival_ns)
+        t = ctypes.c_uint64()
+        check(lib().mg_gemm_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending, else the result dict."""
+        r = Result()
+        rc = check(lib().mg_gemm_poll(self._h, ticket, ctypes.byref(r)))
+        return None if rc == PENDING else result_dict(r)
+
+    def wait(self, ticket: int) -> dict:
+        r = Result()
+        check(lib().mg_gemm_wait(self._h, ticket, ctypes.byref(r)))
+        return result_dict(r)
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        check(lib().mg_server_get_stats(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def replay(self, reqs) -> "ctypes.Array":
+        """Open-loop replay of a ctypes Request array (arrival offsets in ns)."""
+        n = len(reqs)
+        res = (Result * max(1, n))()
+        check(lib().mg_server_replay(self._h, n, reqs, res))
+        return res
+
+    def close(self):
+        if self._h:
+            lib().mg_server_destroy(self._h)
+            self._h = _vp()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -3,9 +3,13 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstring>
+#include <mutex>
+#include <utility>
+#include <vector>
 
 #include "common.h"
 #include "gemm_native.h"
+#include "grouped.h"
 #include "split.h"
 
 namespace mg {
@@ -88,6 +92,84 @@ int validate_problem(const char *what, int64_t m, int64_t n, int64_t k, double a
 }
 
 static int64_t esize(int dtype) { return dtype == MG_F64 ? 8 : dtype == MG_F32 ? 4 : 0; }
+
+// Validates every problem of a batch and that no output overlaps another
+// problem's output or any operand.
+int validate_batch(int dtype, int64_t count, const mg_problem *probs) {
+  const int64_t es = esize(dtype);
+  if (es == 0) {
+    set_error("unknown dtype %d", dtype);
+    return MG_ERR_INVALID_ARG;
+  }
+  if (count < 0 || (count > 0 && probs == nullptr) || count > ((int64_t)1 << 30)) {
+    set_error("bad problem count %lld or NULL problem array", (long long)count);
+    return MG_ERR_INVALID_ARG;
+  }
+  char what[64];
+  struct Span {
+    uintptr_t lo, hi;
+    int64_t idx;
+  };
+  std::vector<Span> cs, ops;
+  for (int64_t i = 0; i < count; ++i) {
+    const mg_problem &q = probs[i];
+    snprintf(what, sizeof(what), "problem %lld", (long long)i);
+    int rc = validate_problem(what, q.m, q.n, q.k, q.alpha, q.A, q.lda, q.B, q.ldb, q.beta, q.C,
+                              q.ldc, es);
+    if (rc != MG_OK) return rc;
+    if (q.m == 0 || q.n == 0) continue;
+    Span c;
+    byte_span(q.C, q.m, q.n, q.ldc, es, c.lo, c.hi);
+    c.idx = i;
+    cs.push_back(c);
+    if (q.k > 0 && q.alpha != 0.0) {
+      Span a, b;
+      byte_span(q.A, q.m, q.k, q.lda, es, a.lo, a.hi);
+      byte_span(q.B, q.k, q.n, q.ldb, es, b.lo, b.hi);
+      a.idx = b.idx = i;
+      ops.push_back(a);
+      ops.push_back(b);
+    }
+  }
+  std::sort(cs.begin(), cs.end(), [](const Span &x, const Span &y) { return x.lo < y.lo; });
+  for (size_t i = 1; i < cs.size(); ++i)
+    if (cs[i].lo < cs[i - 1].hi) {
+      set_error("outputs of problems %lld and %lld overlap", (long long)cs[i - 1].idx,
+                (long long)cs[i].idx);
+      return MG_ERR_INVALID_ARG;
+    }
+  for (const Span &o : ops) {
+    // last output starting below o.hi; outputs are disjoint, so ends are sorted too
+    auto it = std::lower_bound(cs.begin(), cs.end(), o.hi,
+                               [](const Span &x, uintptr_t v) { return x.lo < v; });
+    if (it != cs.begin() && std::prev(it)->hi > o.lo) {
+      set_error("an operand of problem %lld overlaps the output of problem %lld",
+                (long long)o.idx, (long long)std::prev(it)->idx);
+      return MG_ERR_INVALID_ARG;
+    }
+  }
+  return MG_OK;
+}
+
+// One-shot batches: plans whose device memory is released once the event
+// recorded after their launch has completed.
+std::mutex g_deferred_mu;
+std::vector<std::pair<Plan *, hipEvent_t>> g_deferred;
+
+void reap_deferred(bool wait) {
+  std::lock_guard<std::mutex> lk(g_deferred_mu);
+  std::vector<std::pair<Plan *, hipEvent_t>> keep;
+  for (auto &pe : g_deferred) {
+    if (wait) (void)hipEventSynchronize(pe.second);
+    if (hipEventQuery(pe.second) == hipSuccess) {
+      plan_destroy(pe.first);
+      (void)hipEventDestroy(pe.second);
+    } else {
+      keep.push_back(pe);
+    }
+  }
+  g_deferred.swap(keep);
+}
 
 }  // namespace mg
 
@@ -222,17 +304,151 @@ int mg_gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double 
   if (rc != MG_OK) return rc;
   rc = validate_problem("gemm_split", m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, 8);
   if (rc != MG_OK) return rc;
-  if (workspace != nullptr) {
-    const bool reads_ab = k > 0 && alpha != 0.0;
-    if ((reads_ab && spans_overlap(workspace, 1, workspace_bytes, workspace_bytes, C, m, n, ldc, 8)) ||
-        (reads_ab && spans_overlap(workspace, 1, workspace_bytes, workspace_bytes, A, m, k, lda, 8)) ||
-        (reads_ab && spans_overlap(workspace, 1, workspace_bytes, workspace_bytes, B, k, n, ldb, 8))) {
+  const bool reads_ab = k > 0 && alpha != 0.0;
+  if (workspace != nullptr && workspace_bytes > 0 && reads_ab && m > 0 && n > 0) {
+    const uintptr_t w0 = reinterpret_cast<uintptr_t>(workspace);
+    const uintptr_t w1 = w0 + (uintptr_t)workspace_bytes;
+    uintptr_t lo, hi;
+    bool bad = false;
+    byte_span(C, m, n, ldc, 8, lo, hi);
+    bad |= lo < w1 && w0 < hi;
+    byte_span(A, m, k, lda, 8, lo, hi);
+    bad |= lo < w1 && w0 < hi;
+    byte_span(B, k, n, ldb, 8, lo, hi);
+    bad |= lo < w1 && w0 < hi;
+    if (bad) {
       set_error("workspace overlaps A, B or C");
       return MG_ERR_INVALID_ARG;
     }
   }
   return gemm_split(algo, slices, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, workspace,
                     workspace_bytes, static_cast<hipStream_t>(stream));
+}
+
+int mg_grouped_class_info(int cls, int *bm, int *bn) {
+  clear_error();
+  int a = 0, b = 0;
+  if (grouped_class_tile(cls, &a, &b) != MG_OK) {
+    set_error("unknown tile class %d", cls);
+    return MG_ERR_INVALID_ARG;
+  }
+  if (bm) *bm = a;
+  if (bn) *bn = b;
+  return MG_OK;
+}
+
+int mg_tune_bucket(int64_t m, int64_t n, int64_t k) { return tune_bucket(m, n, k); }
+
+int mg_tune_default(int dtype, mg_tune_table *out) {
+  clear_error();
+  if (out == nullptr || esize(dtype) == 0) {
+    set_error("bad dtype or NULL table");
+    return MG_ERR_INVALID_ARG;
+  }
+  out->dtype = dtype;
+  for (int bm = 0; bm < kTuneEdges; ++bm)
+    for (int bn = 0; bn < kTuneEdges; ++bn)
+      for (int bk = 0; bk < kTuneEdges; ++bk)
+        out->cls[(bm * kTuneEdges + bn) * kTuneEdges + bk] =
+            heuristic_class(tune_bucket_rep(bm), tune_bucket_rep(bn));
+  return MG_OK;
+}
+
+int mg_autotune(int dtype, int reps, void *stream, mg_tune_table *out) {
+  clear_error();
+  if (out == nullptr || esize(dtype) == 0 || reps < 1) {
+    set_error("bad dtype, reps or NULL table");
+    return MG_ERR_INVALID_ARG;
+  }
+  return autotune(dtype, reps, static_cast<hipStream_t>(stream), out);
+}
+
+int mg_plan_create(int dtype, int64_t count, const mg_problem *probs, const mg_tune_table *table,
+                   mg_plan **out) {
+  clear_error();
+  if (out == nullptr) {
+    set_error("out is NULL");
+    return MG_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  int rc = validate_batch(dtype, count, probs);
+  if (rc != MG_OK) return rc;
+  if (table != nullptr && table->dtype != dtype) {
+    set_error("tuning table is for dtype %d, plan is %d", table->dtype, dtype);
+    return MG_ERR_INVALID_ARG;
+  }
+  Plan *p = nullptr;
+  rc = plan_create(dtype, count, probs, table, &p);
+  if (rc != MG_OK) return rc;
+  *out = reinterpret_cast<mg_plan *>(p);
+  return MG_OK;
+}
+
+int mg_plan_launch(mg_plan *plan, void *stream) {
+  clear_error();
+  if (plan == nullptr) {
+    set_error("plan is NULL");
+    return MG_ERR_INVALID_ARG;
+  }
+  return plan_launch(reinterpret_cast<Plan *>(plan), static_cast<hipStream_t>(stream), true);
+}
+
+int mg_plan_launch_direct(mg_plan *plan, void *stream) {
+  clear_error();
+  if (plan == nullptr) {
+    set_error("plan is NULL");
+    return MG_ERR_INVALID_ARG;
+  }
+  return plan_launch(reinterpret_cast<Plan *>(plan), static_cast<hipStream_t>(stream), false);
+}
+
+int mg_plan_get_stats(const mg_plan *plan, mg_plan_stats *out) {
+  clear_error();
+  if (plan == nullptr || out == nullptr) {
+    set_error("plan or out is NULL");
+    return MG_ERR_INVALID_ARG;
+  }
+  *out = plan_stats(reinterpret_cast<const Plan *>(plan));
+  return MG_OK;
+}
+
+int mg_plan_destroy(mg_plan *plan) {
+  clear_error();
+  plan_destroy(reinterpret_cast<Plan *>(plan));
+  return MG_OK;
+}
+
+int mg_gemm_batched(int dtype, int algo, int64_t count, const mg_problem *probs, void *stream) {
+  clear_error();
+  if (algo != MG_NATIVE) {
+    set_error("batched GEMM supports MG_NATIVE only");
+    return MG_ERR_UNSUPPORTED;
+  }
+  reap_deferred(false);
+  int rc = validate_batch(dtype, count, probs);
+  if (rc != MG_OK) return rc;
+  if (count == 0) return MG_OK;
+  Plan *p = nullptr;
+  rc = plan_create(dtype, count, probs, nullptr, &p);
+  if (rc != MG_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = plan_launch(p, s, false);
+  hipEvent_t ev = nullptr;
+  if (rc == MG_OK && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess &&
+      hipEventRecord(ev, s) == hipSuccess) {
+    std::lock_guard<std::mutex> lk(g_deferred_mu);
+    g_deferred.emplace_back(p, ev);
+    return MG_OK;
+  }
+  // could not defer: wait for the stream, then free
+  if (ev) (void)hipEventDestroy(ev);
+  (void)hipStreamSynchronize(s);
+  plan_destroy(p);
+  if (rc == MG_OK) {
+    set_error("could not record completion event");
+    return MG_ERR_HIP;
+  }
+  return rc;
 }
 
 }  // extern "C"

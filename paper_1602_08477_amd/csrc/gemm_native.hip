@@ -129,10 +129,11 @@ int tile_cfg_info(int dtype, int cfg, int *bm, int *bn, int *bk, int *threads) {
 int pick_tile_cfg(int dtype, int64_t m, int64_t n, int64_t k) {
   (void)dtype;
   (void)k;
-  // Largest tile that still gives every CU at least two workgroups; the
-  // smallest tile otherwise.
+  // Measured on MI355X (FP64): 64x64 tiles (two workgroups per CU) beat
+  // 128x128 (one per CU) from n = 2048 up; below that, the largest tile
+  // that still gives every CU at least two workgroups.
   const int64_t want = 2 * 256;
-  for (int c = 0; c < kNumCfgs; ++c) {
+  for (int c = 2; c < kNumCfgs; ++c) {
     const int64_t tiles = ceil_div(m, kCfgs[c].bm) * ceil_div(n, kCfgs[c].bn);
     if (tiles >= want) return c;
   }

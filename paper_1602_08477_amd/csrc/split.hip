@@ -188,7 +188,6 @@ struct SplitMma;
 template <>
 struct SplitMma<MG_SPLIT_I8> {
   typedef i4v acc_t;
-  static constexpr int ESZ = 1;
   static constexpr int CHUNK_STAGES = 0;  // INT32 accumulates the diagonal directly
   __device__ static __forceinline__ acc_t mma(i4v a, i4v b, acc_t c) {
     return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
@@ -198,7 +197,6 @@ struct SplitMma<MG_SPLIT_I8> {
 template <>
 struct SplitMma<MG_SPLIT_BF16> {
   typedef f4v acc_t;
-  static constexpr int ESZ = 2;
   static constexpr int CHUNK_STAGES = 4;  // 256 k: 256 * 255^2 < 2^24 keeps FP32 exact
   __device__ static __forceinline__ acc_t mma(i4v a, i4v b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, a),

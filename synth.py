@@ -201,3 +201,15 @@ def poisson_gaps(seed: int, stream: int, count: int, rate: float, start: int = 0
     """Exponential inter-arrival gaps in seconds for a Poisson process."""
     u = uniform_unit(seed, stream, count, start)
     return -np.log1p(-u) / rate
+
+
+def batch_shapes(seed: int, count: int, lo: int = 16, hi: int = 512):
+    """(count, 3) int64 array of (m, n, k), each log-uniform in [lo, hi]
+    (independent draws from the sizes stream)."""
+    v = log_uniform_int(seed, STREAM_SIZES, 3 * count, lo, hi)
+    return v.reshape(count, 3)
+
+
+def flat_uniform(seed: int, stream: int, count: int, device=None):
+    """One long U[-1,1) vector (batched operands are carved out of it)."""
+    return uniform_pm1(seed, stream, count, device=device)

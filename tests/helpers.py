@@ -47,3 +47,28 @@ def elementwise_bound(alpha, A, B, beta, C, k, u=U64):
 def log(msg):
     print(msg, flush=True)
     sys.stdout.flush()
+
+
+def make_batch(seed, shapes, dtype=None, align=32, alpha=1.0, beta=1.0, device="cuda"):
+    """Device operands for a batch: A, B, C of every problem carved from three
+    flat U[-1,1) buffers at 256-byte aligned offsets.  Returns
+    (views [(A, B, C)], flat buffers, problem descriptors)."""
+    import torch
+    import paper_1602_08477_amd as mg
+    dtype = dtype or torch.float64
+    offs = {"A": [], "B": [], "C": []}
+    tot = {"A": 0, "B": 0, "C": 0}
+    for m, n, k in shapes:
+        for key, sz in (("A", m * k), ("B", k * n), ("C", m * n)):
+            offs[key].append(tot[key])
+            tot[key] += -(-sz // align) * align
+    flats = {key: synth.flat_uniform(seed, i, max(tot[key], 1), device=device).to(dtype)
+             for i, key in enumerate(("A", "B", "C"))}
+    views, probs = [], []
+    for i, (m, n, k) in enumerate(shapes):
+        A = flats["A"][offs["A"][i]: offs["A"][i] + m * k].view(m, k)
+        B = flats["B"][offs["B"][i]: offs["B"][i] + k * n].view(k, n)
+        C = flats["C"][offs["C"][i]: offs["C"][i] + m * n].view(m, n)
+        views.append((A, B, C))
+        probs.append(mg.problem(A, B, C, alpha, beta))
+    return views, flats, probs

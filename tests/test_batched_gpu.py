@@ -1,0 +1,178 @@
+"""Batched uneven GEMMs in one persistent launch (needs a GPU).
+
+Each problem must match the oracle (FP64: 1e-13 and the per-element rounding
+bound; FP32: 1e-5 on FP32-rounded inputs).  Every tile runs the same k-loop as
+the single-problem kernel whatever its tile class, so each batched result must
+also equal the single-problem library call bit for bit ("alone" vs "in the
+mix").  Graph replays are checked against eager launches, several times, with
+eager work in between.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import U32, elementwise_bound, log, make_batch
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+mg = pytest.importorskip("paper_1602_08477_amd")
+
+
+def check_problem(A, B, C0, got, alpha, beta, f32=False):
+    A = A.double().cpu().numpy()
+    B = B.double().cpu().numpy()
+    C0 = C0.double().cpu().numpy()
+    got = got.double().cpu().numpy()
+    ref = oracle.dgemm(alpha, A, B, beta, C0)
+    err = oracle.rel_fro_err(got, ref)
+    bound = elementwise_bound(alpha, A, B, beta, C0, A.shape[1], u=U32 if f32 else 2.0 ** -53)
+    assert err <= (1e-5 if f32 else 1e-13), err
+    assert (np.abs(got - ref) <= bound).all()
+    return err
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_batch_matches_oracle_and_single_calls(dt):
+    dtype = torch.float64 if dt == "f64" else torch.float32
+    code = mg.F64 if dt == "f64" else mg.F32
+    shapes = [tuple(int(x) for x in s) for s in synth.batch_shapes(81, 60, 1, 300)]
+    shapes += [(1, 1, 1), (33, 1, 7), (1, 40, 513), (128, 64, 16), (65, 65, 65)]
+    views, flats, probs = make_batch(81, shapes, dtype=dtype, alpha=1.5, beta=0.5)
+    C0 = [c.clone() for _, _, c in views]
+    plan = mg.Plan(code, probs)
+    plan.launch()
+    torch.cuda.synchronize()
+    st = plan.stats()
+    log(f"batch {dt}: {st}")
+    assert st["problems"] == len(shapes) and st["graph"] == 1
+    worst = 0.0
+    for (A, B, C), c0 in zip(views, C0):
+        worst = max(worst, check_problem(A, B, c0, C, 1.5, 0.5, f32=(dt == "f32")))
+        alone = c0.clone()
+        mg.gemm(A, B, alone, 1.5, 0.5)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, C), "batched result differs from the single call"
+    log(f"batch {dt}: worst rel_fro_err {worst:.3e}")
+
+
+def test_tile_classes_agree_bitwise():
+    """Forcing each tile class through the tuning table gives identical bits."""
+    shapes = [(97, 131, 77), (200, 64, 300), (31, 257, 45)]
+    outs = []
+    for c in range(mg.NUM_GROUPED_CLASSES):
+        views, flats, probs = make_batch(82, shapes)
+        t = mg.TuneTable.from_list(mg.F64, [c] * mg.TUNE_BUCKETS)
+        plan = mg.Plan(mg.F64, probs, t)
+        plan.launch()
+        torch.cuda.synchronize()
+        assert plan.stats()["tiles_per_class"][c] == plan.stats()["tiles"]
+        outs.append([C.clone() for _, _, C in views])
+    for o in outs[1:]:
+        assert all(torch.equal(a, b) for a, b in zip(outs[0], o))
+
+
+def test_graph_replays_match_eager():
+    shapes = [tuple(int(x) for x in s) for s in synth.batch_shapes(83, 40, 16, 256)]
+    views, flats, probs = make_batch(83, shapes, beta=0.0)
+    plan = mg.Plan(mg.F64, probs)
+    plan.launch(graph=False)
+    torch.cuda.synchronize()
+    eager = [C.clone() for _, _, C in views]
+    for rep in range(4):
+        for _, _, C in views:
+            C.fill_(float("nan"))  # eager work between replays; beta=0 ignores it
+        torch.cuda.synchronize()
+        plan.launch(graph=True)
+        torch.cuda.synchronize()
+        assert all(torch.equal(e, C) for e, (_, _, C) in zip(eager, views)), rep
+
+
+def test_special_problems_in_batch():
+    dev = "cuda"
+    d = torch.float64
+    A = synth.matrix(84, 0, 50, 40, device=dev)
+    B = synth.matrix(84, 1, 40, 30, device=dev)
+    nanC = torch.full((50, 30), float("nan"), dtype=d, device=dev)
+    C1 = synth.matrix(84, 2, 50, 30, device=dev)
+    C1_0 = C1.clone()
+    C2 = synth.matrix(84, 3, 50, 30, device=dev)
+    C2_0 = C2.clone()
+    nanA = torch.full((50, 40), float("nan"), dtype=d, device=dev)
+    big = torch.zeros(60, 45, dtype=d, device=dev)
+    Cu = big[1:51, 1:31]  # 8-byte aligned, odd pitch: scalar path
+    empty = torch.empty(0, 30, dtype=d, device=dev)
+    probs = [mg.problem(A, B, nanC, 1.0, 0.0),          # beta = 0 ignores NaN C
+             mg.problem(nanA, B, C1, 0.0, 2.0),         # alpha = 0 ignores NaN A
+             mg.Problem(50, 30, 0, 1.0, 0.5, None, 1, None, 1, C2.data_ptr(), 30),  # k = 0
+             mg.problem(A, B, Cu, 1.0, 0.0),
+             mg.problem(torch.empty(0, 40, dtype=d, device=dev), B, empty, 1.0, 0.0)]
+    plan = mg.Plan(mg.F64, probs)
+    plan.launch()
+    torch.cuda.synchronize()
+    ref = A.cpu().numpy() @ B.cpu().numpy()
+    assert torch.isfinite(nanC).all()
+    assert np.allclose(nanC.cpu().numpy(), ref, rtol=0, atol=1e-13)
+    assert torch.equal(C1, 2.0 * C1_0)
+    assert torch.equal(C2, 0.5 * C2_0)
+    assert np.allclose(Cu.cpu().numpy(), ref, rtol=0, atol=1e-13)
+    assert plan.stats()["scale_tiles"] > 0
+
+
+def test_overlapping_outputs_rejected():
+    C = torch.zeros(64, 64, dtype=torch.float64, device="cuda")
+    A = torch.zeros(64, 64, dtype=torch.float64, device="cuda")
+    p1 = mg.problem(A[:40], A, C[:40], 1.0, 0.0)
+    p2 = mg.problem(A[:30], A, C[30:60], 1.0, 0.0)
+    with pytest.raises(mg.MgError, match="overlap"):
+        mg.Plan(mg.F64, [p1, p2])
+    p3 = mg.problem(A, A, A, 1.0, 0.0)  # C overlaps its own A
+    with pytest.raises(mg.MgError, match="overlaps"):
+        mg.Plan(mg.F64, [p3])
+
+
+def test_one_shot_batched_matches_plan():
+    shapes = [tuple(int(x) for x in s) for s in synth.batch_shapes(85, 30, 16, 200)]
+    v1, f1, p1 = make_batch(85, shapes)
+    v2, f2, p2 = make_batch(85, shapes)
+    mg.Plan(mg.F64, p1).launch()
+    mg.gemm_batched(p2, mg.F64)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a[2], b[2]) for a, b in zip(v1, v2))
+
+
+def test_autotune_table_valid():
+    t = mg.autotune(mg.F64, reps=1)
+    vals = t.to_list()
+    assert len(vals) == mg.TUNE_BUCKETS and all(0 <= v < mg.NUM_GROUPED_CLASSES for v in vals)
+    log(f"autotune classes histogram: {np.bincount(vals, minlength=3).tolist()}")
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_config4_2000_problems_sampled(dt):
+    """Workload 4: 2000 problems, m, n, k log-uniform in [16, 512], one
+    persistent graph launch with an autotuned table; 100 sampled problems
+    against the oracle, every output finite."""
+    dtype = torch.float64 if dt == "f64" else torch.float32
+    code = mg.F64 if dt == "f64" else mg.F32
+    seed = synth.config_seed(4)
+    shapes = [tuple(int(x) for x in s) for s in synth.batch_shapes(seed, 2000)]
+    views, flats, probs = make_batch(seed, shapes, dtype=dtype)
+    C0 = {}
+    idx = np.unique(synth.log_uniform_int(seed, 11, 100, 1, 1999))
+    idx = np.concatenate([[0, 1999], idx])
+    for i in idx:
+        C0[int(i)] = views[int(i)][2].clone()
+    table = mg.autotune(code, reps=1)
+    plan = mg.Plan(code, probs, table)
+    plan.launch()
+    torch.cuda.synchronize()
+    log(f"config4 {dt}: {plan.stats()}")
+    worst = 0.0
+    for i in C0:
+        A, B, C = views[i]
+        worst = max(worst, check_problem(A, B, C0[i], C, 1.0, 1.0, f32=(dt == "f32")))
+    log(f"config4 {dt}: worst sampled rel_fro_err {worst:.3e}")
+    assert all(torch.isfinite(f).all() for f in flats.values())

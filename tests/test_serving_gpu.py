@@ -1,0 +1,158 @@
+"""The continuous-batching GEMM server (needs a GPU).
+
+Checks: results against the oracle; every request's result is bit-identical
+when it runs alone and when it runs inside a Poisson mix (the per-request
+arithmetic depends only on its own shape); admission keeps the admitted
+bytes within the budget and the slot limit; oversized requests and a full
+queue are rejected; batches really contain several requests and batches on
+different streams overlap in time.
+"""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import log
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+mg = pytest.importorskip("paper_1602_08477_amd")
+
+
+def make_trace(seed, count, rate, lo, hi, split_frac=0.3):
+    """Poisson arrivals, square n log-uniform in [lo, hi], a split_frac share
+    of split-INT8 requests, operands U[-1,1) per request."""
+    gaps = synth.poisson_gaps(seed, synth.STREAM_ARRIVALS, count, rate)
+    t = np.cumsum(gaps) - gaps[0]
+    ns = synth.log_uniform_int(seed, synth.STREAM_SIZES, count, lo, hi)
+    mix = synth.uniform_unit(seed, synth.STREAM_MIX, count)
+    algos = np.where(mix < split_frac, mg.SPLIT_I8, mg.NATIVE)
+    ops = []
+    for i, n in enumerate(ns):
+        n = int(n)
+        A = synth.uniform_pm1(seed + i, 0, n * n, device="cuda").view(n, n)
+        B = synth.uniform_pm1(seed + i, 1, n * n, device="cuda").view(n, n)
+        C = synth.uniform_pm1(seed + i, 2, n * n, device="cuda").view(n, n)
+        ops.append((A, B, C, C.clone()))
+    reqs = (mg.Request * count)()
+    for i, (A, B, C, _) in enumerate(ops):
+        reqs[i] = mg.Request(mg.F64, int(algos[i]), mg.problem(A, B, C, 1.0, 1.0),
+                             int(t[i] * 1e9))
+    return reqs, ops, algos
+
+
+def test_submit_wait_matches_oracle():
+    with mg.Server(n_streams=2) as srv:
+        cases = []
+        for i, (n, algo) in enumerate([(33, mg.NATIVE), (200, mg.SPLIT_I8), (129, mg.NATIVE),
+                                       (64, mg.SPLIT_BF16)]):
+            A = synth.matrix(90 + i, 0, n, n + 3, device="cuda")
+            B = synth.matrix(90 + i, 1, n + 3, n, device="cuda")
+            C = synth.matrix(90 + i, 2, n, n, device="cuda")
+            C0 = C.clone()
+            t = srv.submit(A, B, C, 1.5, 0.5, algo=algo)
+            cases.append((t, A, B, C, C0, algo))
+        for t, A, B, C, C0, algo in cases:
+            r = srv.wait(t)
+            assert r["status"] == mg.OK
+            assert r["t_arrival_ns"] <= r["t_submit_ns"] <= r["t_admit_ns"] <= r["t_launch_ns"] \
+                <= r["t_done_ns"]
+            ref = oracle.dgemm(1.5, A.cpu().numpy(), B.cpu().numpy(), 0.5, C0.cpu().numpy())
+            err = oracle.rel_fro_err(C.cpu().numpy(), ref)
+            assert err <= (1e-13 if algo == mg.NATIVE else 1e-12), (algo, err)
+        with pytest.raises(mg.MgError):
+            srv.poll(cases[0][0])  # ticket released after the result was taken
+
+
+def test_alone_equals_in_mix_and_oracle():
+    seed = synth.config_seed(5, 1)
+    count = 400
+    reqs, ops, algos = make_trace(seed, count, 4000.0, 32, 256)
+    with mg.Server(n_streams=4, max_batch=32) as srv:
+        res = srv.replay(reqs)
+        st = srv.stats()
+    log(f"mix stats: {st}")
+    assert all(r.status == mg.OK for r in res)
+    assert st["completed"] == count and st["max_batch_seen"] > 1
+    mixed = [C.clone() for _, _, C, _ in ops]
+    # every request alone, on a fresh server, from the same initial C
+    with mg.Server(n_streams=1) as alone:
+        for i, (A, B, C, C0) in enumerate(ops):
+            C.copy_(C0)
+            t = alone.submit(A, B, C, 1.0, 1.0, algo=int(algos[i]))
+            assert alone.wait(t)["status"] == mg.OK
+            assert torch.equal(C, mixed[i]), f"request {i} differs alone vs in the mix"
+    # a sample against the oracle
+    for i in range(0, count, 37):
+        A, B, _, C0 = ops[i]
+        ref = oracle.dgemm(1.0, A.cpu().numpy(), B.cpu().numpy(), 1.0, C0.cpu().numpy())
+        err = oracle.rel_fro_err(mixed[i].cpu().numpy(), ref)
+        assert err <= (1e-13 if algos[i] == mg.NATIVE else 1e-12), (i, err)
+    # batches on different streams overlapped in time
+    iv = sorted({(r.batch_id, r.t_launch_ns, r.t_done_ns) for r in res}, key=lambda x: x[1])
+    overlaps = sum(1 for a, b in zip(iv, iv[1:]) if b[1] < a[2])
+    log(f"batches {len(iv)}, overlapping consecutive batches {overlaps}")
+    assert overlaps > 0
+
+
+def test_admission_respects_budget_and_slots():
+    n = 256
+    per_req = 3 * n * n * 8
+    budget = 3 * per_req + 1000
+    with mg.Server(n_streams=4, max_slots=2, hbm_budget_bytes=budget) as srv:
+        ops, tickets = [], []
+        for i in range(24):
+            A = synth.matrix(95, 0, n, n, device="cuda")
+            B = synth.matrix(95, 1, n, n, device="cuda")
+            C = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+            ops.append((A, B, C))
+            tickets.append(srv.submit(A, B, C))
+        for t in tickets:
+            assert srv.wait(t)["status"] == mg.OK
+        st = srv.stats()
+        assert st["max_inflight_bytes"] <= budget
+        assert st["max_slots_used"] <= 2
+        ref = (ops[0][0] @ ops[0][1])
+        assert all(torch.allclose(C, ref, rtol=0, atol=1e-12) for _, _, C in ops)
+        big = torch.zeros(512, 512, dtype=torch.float64, device="cuda")
+        with pytest.raises(mg.MgError) as ei:
+            srv.submit(big, big.clone(), big.clone())
+        assert ei.value.code == mg.ERR_NO_MEMORY
+        assert srv.stats()["rejected_memory"] == 1
+
+
+def test_queue_full_is_busy():
+    n = 4096
+    A = synth.matrix(96, 0, n, n, device="cuda")
+    B = synth.matrix(96, 1, n, n, device="cuda")
+    Cs = [torch.zeros(n, n, dtype=torch.float64, device="cuda") for _ in range(8)]
+    with mg.Server(n_streams=1, max_slots=1, max_queue=2) as srv:
+        tickets, busy = [], 0
+        for C in Cs:
+            try:
+                tickets.append(srv.submit(A, B, C))
+            except mg.MgError as e:
+                assert e.code == mg.ERR_BUSY
+                busy += 1
+        for t in tickets:
+            assert srv.wait(t)["status"] == mg.OK
+        assert busy > 0 and srv.stats()["rejected_busy"] == busy
+
+
+def test_invalid_request_rejected_before_queueing():
+    with mg.Server(n_streams=1) as srv:
+        A = torch.zeros(8, 8, dtype=torch.float64, device="cuda")
+        r = mg.Request(mg.F64, mg.NATIVE, mg.Problem(8, 8, 8, 1.0, 0.0, A.data_ptr(), 8,
+                                                       A.data_ptr(), 8, A.data_ptr(), 8), 0)
+        t = ctypes.c_uint64()
+        assert mg.lib().mg_gemm_submit(srv._h, ctypes.byref(r), ctypes.byref(t)) \
+            == mg.ERR_INVALID_ARG
+        r.algo = mg.SPLIT_I8
+        r.dtype = mg.F32
+        assert mg.lib().mg_gemm_submit(srv._h, ctypes.byref(r), ctypes.byref(t)) \
+            == mg.ERR_UNSUPPORTED
+        assert srv.stats()["submitted"] == 0

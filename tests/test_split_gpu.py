@@ -211,3 +211,17 @@ def test_config3_n4096_sampled(kind):
         acc = acc + np.ldexp(P[d], -bits * d)
     want = np.ldexp(acc, (Eo[:, None] + Fo[None, :]).astype(np.int32))
     assert np.array_equal(got, want)
+
+
+def test_workspace_below_operands_is_not_an_overlap():
+    """Regression: a workspace at lower addresses than the operands (allocated
+    first) was once reported as overlapping them."""
+    m, n, k = 64, 80, 96
+    algo = ALGOS["i8"]
+    s = mg.split_default_slices(algo)
+    ws = mg.split_workspace(algo, s, m, n, k)
+    A, B, C = spread(74, m, n, k)
+    dA, dB, dC = to_dev(A), to_dev(B), to_dev(C)
+    mg.gemm_split(dA, dB, dC, 1.0, 1.0, algo=algo, slices=s, workspace=ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(dC.cpu().numpy(), osplit.split_gemm(1.0, A, B, 1.0, C, s, "i8"))

@@ -330,6 +330,9 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline only (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="also run one plain device-to-device copy of this many GiB "
+                         "(reference kernel for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the GEMM path "
@@ -345,6 +348,14 @@ def main():
     n = args.n
     eprint(f"bench: native FP64 n={n} steps={args.steps} warmup={args.warmup}")
     ms_step, kern_ms, err = bench_native(n, args.steps, args.warmup)
+    if args.copy_gib > 0:
+        nb = int(args.copy_gib * 2 ** 30) // 8
+        src = torch.ones(nb, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
     flop = 2.0 * n ** 3
     value = flop / ms_step / 1e9
     achieved = flop / kern_ms / 1e9

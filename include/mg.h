@@ -123,7 +123,7 @@ int mg_pick_tile_cfg(int dtype, int64_t m, int64_t n, int64_t k);
  */
 typedef struct mg_split_layout {
   int64_t mp, np, kp, elem_bytes;
-  int64_t e_off, f_off, a_off, b_off, total_bytes;
+  int64_t e_off, f_off, a_off, b_off, p_off, total_bytes;
 } mg_split_layout;
 
 /* Default slice count: 7 for MG_SPLIT_I8, 6 for MG_SPLIT_BF16. */
@@ -252,6 +252,13 @@ typedef struct mg_server_opts {
   int64_t hbm_budget_bytes; /* admission cap on admitted request bytes       */
   const mg_tune_table *table; /* tile classes for native requests (NULL:
                                  heuristic); copied at creation              */
+  /* Host simulation (capacity planning and host-logic tests): when nonzero
+   * no HIP call is made and operands are never touched; a batch "runs" for
+   * sim_launch_ns + (its FLOPs) / (sim_tflops * 1e12) seconds of host time,
+   * with FLOPs counted as 2mnk (native) or pairs*2mnk at 2x rate (split). */
+  int32_t simulate;
+  double sim_tflops;
+  int64_t sim_launch_ns;
 } mg_server_opts;
 
 typedef struct mg_request {

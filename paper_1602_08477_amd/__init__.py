@@ -42,7 +42,7 @@ class MgError(RuntimeError):
 
 class SplitLayout(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
-                ("mp", "np", "kp", "elem_bytes", "e_off", "f_off", "a_off", "b_off",
+                ("mp", "np", "kp", "elem_bytes", "e_off", "f_off", "a_off", "b_off", "p_off",
                  "total_bytes")]
 
 
@@ -331,7 +331,8 @@ def gemm_batched(probs, dtype: int = F64, stream=None):
 class ServerOpts(ctypes.Structure):
     _fields_ = [("n_streams", _int), ("max_slots", _int), ("max_queue", _int),
                 ("max_batch", _int), ("hbm_budget_bytes", _i64),
-                ("table", ctypes.POINTER(TuneTable))]
+                ("table", ctypes.POINTER(TuneTable)), ("simulate", ctypes.c_int32),
+                ("sim_tflops", _dbl), ("sim_launch_ns", _i64)]
 
 
 class Request(ctypes.Structure):
@@ -374,16 +375,22 @@ class Server:
     """Continuous-batching GEMM server (mg_server_*)."""
 
     def __init__(self, n_streams=4, max_slots=256, max_queue=1 << 20, max_batch=64,
-                 hbm_budget_bytes=64 << 30, table: TuneTable | None = None):
+                 hbm_budget_bytes=64 << 30, table: TuneTable | None = None,
+                 simulate: bool = False, sim_tflops: float = 50.0, sim_launch_ns: int = 20000):
+        """``simulate=True``: host simulation, no GPU work (see mg_server_opts)."""
         self._table = table
         o = ServerOpts(n_streams, max_slots, max_queue, max_batch, hbm_budget_bytes,
-                       None if table is None else ctypes.pointer(table))
+                       None if table is None else ctypes.pointer(table), int(simulate),
+                       sim_tflops, sim_launch_ns)
         h = _vp()
         check(lib().mg_server_create(ctypes.byref(o), ctypes.byref(h)))
         self._h = h
 
     def submit(self, A, B, C, alpha=1.0, beta=0.0, algo=NATIVE, t_arrival_ns=0) -> int:
-        r = Request(_dtype_code(C), algo, problem(A, B, C, alpha, beta), t_arrival_ns)
+        return self.submit_request(Request(_dtype_code(C), algo, problem(A, B, C, alpha, beta),
+                                           t_arrival_ns))
+
+    def submit_request(self, r: Request) -> int:
         t = ctypes.c_uint64()
         check(lib().mg_gemm_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
         return t.value

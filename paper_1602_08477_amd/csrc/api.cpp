@@ -266,6 +266,7 @@ int mg_split_layout_query(int algo, int slices, int64_t m, int64_t n, int64_t k,
   out->f_off = L.f_off;
   out->a_off = L.a_off;
   out->b_off = L.b_off;
+  out->p_off = L.p_off;
   out->total_bytes = L.total;
   return MG_OK;
 }

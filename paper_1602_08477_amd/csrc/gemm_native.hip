@@ -10,15 +10,15 @@ namespace {
 
 constexpr int kGroupM = 8;  // tile-rows walked together by the raster
 
-template <typename T, int BM, int BN, bool VEC_OK>
-__global__ __launch_bounds__(kTileThreads) void gemm_native_kernel(GemmArgs<T> g, int tiles_m,
-                                                                   int tiles_n) {
+template <typename T, int BM, int BN, bool VEC_OK, int WGM, int WGN, int BKM>
+__global__ __launch_bounds__((TileShape<T, BM, BN, WGM, WGN, BKM>::THREADS)) void gemm_native_kernel(
+    GemmArgs<T> g, int tiles_m, int tiles_n) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T *smem = reinterpret_cast<T *>(lds_raw);
   int tm, tn;
   const int t = xcd_remap(blockIdx.x, tiles_m * tiles_n);
   grouped_tile(t, tiles_m, tiles_n, kGroupM, tm, tn);
-  gemm_tile<T, BM, BN, VEC_OK>(g, tm * BM, tn * BN, smem);
+  gemm_tile<T, BM, BN, VEC_OK, WGM, WGN, BKM>(g, tm * BM, tn * BN, smem);
 }
 
 // C <- beta*C (alpha == 0 or k == 0).  beta == 0 writes zeros without reading.
@@ -34,21 +34,25 @@ __global__ void scale_kernel(T *C, int64_t ldc, int m, int n, T beta) {
 }
 
 struct CfgDesc {
-  int bm, bn;
+  int bm, bn, wgm, wgn, bkm;
 };
-constexpr CfgDesc kCfgs[] = {{128, 128}, {128, 64}, {64, 64}, {64, 32}, {32, 32}};
+// Work divisions: macro-tile, wavefront grid, k-step multiplier.
+constexpr CfgDesc kCfgs[] = {{128, 128, 2, 2, 1}, {128, 64, 2, 2, 1}, {64, 64, 2, 2, 1},
+                             {64, 32, 2, 2, 1},   {32, 32, 2, 2, 1},  {128, 128, 4, 2, 1},
+                             {128, 128, 2, 4, 1}, {64, 64, 2, 2, 2},  {128, 64, 4, 2, 1},
+                             {128, 64, 2, 2, 2}};
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
-template <typename T, int BM, int BN, bool VEC_OK>
+template <typename T, int BM, int BN, bool VEC_OK, int WGM = 2, int WGN = 2, int BKM = 1>
 int launch_one(const GemmArgs<T> &g, hipStream_t s) {
-  typedef TileShape<T, BM, BN> S;
+  typedef TileShape<T, BM, BN, WGM, WGN, BKM> S;
   const int tiles_m = (g.m + BM - 1) / BM, tiles_n = (g.n + BN - 1) / BN;
   const int64_t tiles = (int64_t)tiles_m * tiles_n;
   if (tiles > INT32_MAX) {
     set_error("too many tiles (%lld)", (long long)tiles);
     return MG_ERR_INVALID_ARG;
   }
-  auto kern = gemm_native_kernel<T, BM, BN, VEC_OK>;
+  auto kern = gemm_native_kernel<T, BM, BN, VEC_OK, WGM, WGN, BKM>;
   static bool attr_set = false;  // per template instance
   if (!attr_set) {
     MG_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -56,8 +60,8 @@ int launch_one(const GemmArgs<T> &g, hipStream_t s) {
                                    (int)S::LDS_BYTES));
     attr_set = true;
   }
-  hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(kTileThreads), S::LDS_BYTES, s, g,
-                     tiles_m, tiles_n);
+  hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(S::THREADS), S::LDS_BYTES, s, g, tiles_m,
+                     tiles_n);
   MG_HIP_TRY(hipGetLastError());
   return MG_OK;
 }
@@ -70,6 +74,11 @@ int launch_cfg(int cfg, const GemmArgs<T> &g, hipStream_t s) {
     case 2: return launch_one<T, 64, 64, VEC_OK>(g, s);
     case 3: return launch_one<T, 64, 32, VEC_OK>(g, s);
     case 4: return launch_one<T, 32, 32, VEC_OK>(g, s);
+    case 5: return launch_one<T, 128, 128, VEC_OK, 4, 2, 1>(g, s);
+    case 6: return launch_one<T, 128, 128, VEC_OK, 2, 4, 1>(g, s);
+    case 7: return launch_one<T, 64, 64, VEC_OK, 2, 2, 2>(g, s);
+    case 8: return launch_one<T, 128, 64, VEC_OK, 4, 2, 1>(g, s);
+    case 9: return launch_one<T, 128, 64, VEC_OK, 2, 2, 2>(g, s);
   }
   set_error("unknown tile cfg %d", cfg);
   return MG_ERR_INVALID_ARG;
@@ -121,8 +130,8 @@ int tile_cfg_info(int dtype, int cfg, int *bm, int *bn, int *bk, int *threads) {
   }
   if (bm) *bm = kCfgs[cfg].bm;
   if (bn) *bn = kCfgs[cfg].bn;
-  if (bk) *bk = dtype == MG_F64 ? Mfma<double>::BK : Mfma<float>::BK;
-  if (threads) *threads = kTileThreads;
+  if (bk) *bk = kCfgs[cfg].bkm * (dtype == MG_F64 ? Mfma<double>::BK : Mfma<float>::BK);
+  if (threads) *threads = 64 * kCfgs[cfg].wgm * kCfgs[cfg].wgn;
   return MG_OK;
 }
 
@@ -133,11 +142,11 @@ int pick_tile_cfg(int dtype, int64_t m, int64_t n, int64_t k) {
   // 128x128 (one per CU) from n = 2048 up; below that, the largest tile
   // that still gives every CU at least two workgroups.
   const int64_t want = 2 * 256;
-  for (int c = 2; c < kNumCfgs; ++c) {
+  for (int c = 2; c <= 4; ++c) {
     const int64_t tiles = ceil_div(m, kCfgs[c].bm) * ceil_div(n, kCfgs[c].bn);
     if (tiles >= want) return c;
   }
-  return kNumCfgs - 1;
+  return 4;
 }
 
 int gemm_native(int dtype, int cfg, int64_t m, int64_t n, int64_t k, double alpha, const void *A,

@@ -67,28 +67,35 @@ struct GemmArgs {
 
 constexpr int kTileThreads = 256;
 
-template <typename T, int BM, int BN>
+// Macro-tile BM x BN computed by WGM x WGN wavefronts (each a WM x WN wave
+// tile of 16x16 MFMA blocks), k-step BK = BKM times the type's base step.
+template <typename T, int BM, int BN, int WGM = 2, int WGN = 2, int BKM = 1>
 struct TileShape {
   typedef Mfma<T> M;
+  static constexpr int THREADS = 64 * WGM * WGN;
   static constexpr int VEC = M::VEC;
-  static constexpr int BK = M::BK;
-  static constexpr int PA = 2;  // A chunk-row pitch = BM + 2 chunks
+  static constexpr int BK = M::BK * BKM;
+  static constexpr int ACH = BK / VEC;  // A chunks per tile row
+  // A chunk-row pitch BM + PA: with ACH chunks per row written by consecutive
+  // lanes, PA = 16 / ACH spreads the 16 lanes of a 16-byte LDS write over
+  // all 64 banks.
+  static constexpr int PA = 16 / ACH;
   static constexpr int PB = M::PB;
-  static constexpr int WM = BM / 2, WN = BN / 2;  // wave tile
-  static constexpr int FM = WM / 16, FN = WN / 16;  // MFMA blocks per wave
-  static constexpr int A_CHUNKS = BM * BK / VEC;  // 16-byte chunks per A tile
+  static constexpr int WM = BM / WGM, WN = BN / WGN;  // wave tile
+  static constexpr int FM = WM / 16, FN = WN / 16;    // MFMA blocks per wave
+  static constexpr int A_CHUNKS = BM * BK / VEC;      // 16-byte chunks per A tile
   static constexpr int B_CHUNKS = BK * BN / VEC;
-  static constexpr int NA = A_CHUNKS / kTileThreads;  // per thread
-  static constexpr int NB = B_CHUNKS / kTileThreads;
-  static constexpr int A_STAGE = (BK / VEC) * (BM + PA) * VEC;  // elements
+  static constexpr int NA = A_CHUNKS / THREADS;  // per thread
+  static constexpr int NB = B_CHUNKS / THREADS;
+  static constexpr int A_STAGE = ACH * (BM + PA) * VEC;  // elements
   static constexpr int B_STAGE = BK * (BN + PB);
   static constexpr int STAGE = A_STAGE + B_STAGE;
   static constexpr size_t LDS_BYTES = 2 * STAGE * sizeof(T);
-  static_assert(BM % 32 == 0 && BN % 32 == 0, "tile must be a multiple of 32");
-  static_assert(NA >= 1 && NB >= 1 && A_CHUNKS % kTileThreads == 0 &&
-                    B_CHUNKS % kTileThreads == 0,
+  static_assert(WM % 16 == 0 && WN % 16 == 0 && FM >= 1 && FN >= 1, "wave tile of 16x16 blocks");
+  static_assert(ACH <= 16 && 16 % ACH == 0, "A chunks per row");
+  static_assert(NA >= 1 && NB >= 1 && A_CHUNKS % THREADS == 0 && B_CHUNKS % THREADS == 0,
                 "every thread loads whole chunks");
-  static_assert((BK / VEC) % 4 == 0, "k rounds of 4 lane groups");
+  static_assert(ACH % 4 == 0, "k rounds of 4 lane groups");
 };
 
 // Loads one 16-byte chunk of a row: `left` elements remain in the row from p.
@@ -177,21 +184,21 @@ struct Epilogue<float, VEC_OK> {
 };
 
 // Computes the BM x BN tile of C whose top-left output is (m0, n0).
-// `smem` holds 2 stages of TileShape::STAGE elements.  All 256 lanes of the
-// workgroup must call this together (it contains barriers).
-template <typename T, int BM, int BN, bool VEC_OK>
+// `smem` holds 2 stages of TileShape::STAGE elements.  All THREADS lanes of
+// the workgroup must call this together (it contains barriers).
+template <typename T, int BM, int BN, bool VEC_OK, int WGM = 2, int WGN = 2, int BKM = 1>
 __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &g, int m0, int n0, T *smem) {
-  typedef TileShape<T, BM, BN> S;
+  typedef TileShape<T, BM, BN, WGM, WGN, BKM> S;
   typedef Mfma<T> M;
   typedef typename M::vec_t V;
   typedef typename M::acc_t Acc;
   constexpr int VEC = S::VEC, BK = S::BK;
-  constexpr int ACH = BK / VEC;  // A chunks per tile row
+  constexpr int ACH = S::ACH;    // A chunks per tile row
   constexpr int BCH = BN / VEC;  // B chunks per tile row
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm0 = (wave >> 1) * S::WM, wn0 = (wave & 1) * S::WN;
+  const int wm0 = (wave / WGN) * S::WM, wn0 = (wave % WGN) * S::WN;
   const int gq = lane >> 4, l16 = lane & 15;
 
   // Per-thread global chunk coordinates (fixed across k-tiles).
@@ -200,7 +207,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &g, int m0, int n0, 
   int a_kc[S::NA], a_row[S::NA];
 #pragma unroll
   for (int u = 0; u < S::NA; ++u) {
-    const int q = tid + kTileThreads * u;
+    const int q = tid + S::THREADS * u;
     a_row[u] = q / ACH;
     a_kc[u] = q % ACH;
     const int grow = m0 + a_row[u];
@@ -212,7 +219,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &g, int m0, int n0, 
   int b_r[S::NB], b_c[S::NB], b_left[S::NB];
 #pragma unroll
   for (int u = 0; u < S::NB; ++u) {
-    const int q = tid + kTileThreads * u;
+    const int q = tid + S::THREADS * u;
     b_r[u] = q / BCH;
     b_c[u] = (q % BCH) * VEC;
     const int gcol = n0 + b_c[u];

@@ -46,6 +46,7 @@ struct Lane {
   size_t h_cap = 0;
   int *d_counter = nullptr;  // two counters, 256 bytes apart
   std::vector<Req *> batch;
+  int64_t sim_done_ns = 0;  // host simulation: when the batch "completes"
   bool busy = false;      // owns a batch (being launched or in flight)
   bool launched = false;  // event recorded, waiter may wait
   std::thread waiter;
@@ -74,6 +75,8 @@ struct Server {
   bool stop = false, stop_waiters = false;
   mg_server_stats st{};
   int64_t next_batch = 0;
+  std::mutex sim_mu;               // host simulation: modeled device backlog
+  int64_t sim_device_free_ns = 0;
 };
 
 namespace {
@@ -93,8 +96,37 @@ int ensure_capacity(Lane &L, size_t bytes) {
   return MG_OK;
 }
 
+// Host simulation of a batch: modeled duration, no device work.  Batches on
+// different lanes share the modeled device, so a batch starts when both its
+// lane and the device's backlog allow.
+void simulate_batch(Server *S, Lane &L, int64_t batch_id) {
+  const int64_t t = now_ns();
+  double flops = 0;
+  for (Req *q : L.batch) {
+    q->res.t_launch_ns = t;
+    q->res.batch_id = batch_id;
+    q->res.batch_size = (int)L.batch.size();
+    const mg_problem &p = q->r.p;
+    double f = 2.0 * (double)p.m * (double)p.n * (double)p.k;
+    if (q->r.algo != MG_NATIVE) {
+      const int sl = split_default_slices(q->r.algo);
+      f *= 0.5 * sl * (sl + 1) / 2;
+    }
+    flops += f;
+  }
+  const int64_t dur = S->o.sim_launch_ns + (int64_t)(flops / (S->o.sim_tflops * 1e12) * 1e9);
+  std::lock_guard<std::mutex> lk(S->sim_mu);
+  const int64_t start = std::max(t, S->sim_device_free_ns);
+  S->sim_device_free_ns = start + dur;
+  L.sim_done_ns = start + dur;
+}
+
 // Enqueues one batch on lane L (no lock held; L is owned by this batch).
 void launch_batch(Server *S, Lane &L, int64_t batch_id) {
+  if (S->o.simulate) {
+    simulate_batch(S, L, batch_id);
+    return;
+  }
   const int64_t t = now_ns();
   const int nb = (int)L.batch.size();
   std::vector<mg_problem> p64, p32;
@@ -148,7 +180,7 @@ void launch_batch(Server *S, Lane &L, int64_t batch_id) {
 }
 
 void scheduler_loop(Server *S) {
-  (void)hipSetDevice(S->device);
+  if (!S->o.simulate) (void)hipSetDevice(S->device);
   std::unique_lock<std::mutex> lk(S->mu);
   for (;;) {
     while (!S->waiting.empty()) {
@@ -192,13 +224,19 @@ void scheduler_loop(Server *S) {
 }
 
 void waiter_loop(Server *S, Lane *L) {
-  (void)hipSetDevice(S->device);
+  if (!S->o.simulate) (void)hipSetDevice(S->device);
   std::unique_lock<std::mutex> lk(S->mu);
   for (;;) {
     S->cv_lane.wait(lk, [&] { return L->launched || S->stop_waiters; });
     if (!L->launched) break;
     lk.unlock();
-    const hipError_t e = hipEventSynchronize(L->ev);
+    hipError_t e = hipSuccess;
+    if (S->o.simulate) {
+      const int64_t wait = L->sim_done_ns - now_ns();
+      if (wait > 0) std::this_thread::sleep_for(std::chrono::nanoseconds(wait));
+    } else {
+      e = hipEventSynchronize(L->ev);
+    }
     const int64_t t = now_ns();
     lk.lock();
     for (Req *q : L->batch) {
@@ -232,7 +270,8 @@ void destroy_lanes(Server *S) {
 
 int server_create(const mg_server_opts *o, Server **out) {
   if (o == nullptr || out == nullptr || o->n_streams < 1 || o->n_streams > 8 || o->max_slots < 1 ||
-      o->max_queue < 1 || o->max_batch < 1 || o->hbm_budget_bytes <= 0) {
+      o->max_queue < 1 || o->max_batch < 1 || o->hbm_budget_bytes <= 0 ||
+      (o->simulate && !(o->sim_tflops > 0.0 && o->sim_launch_ns >= 0))) {
     set_error("bad server options");
     return MG_ERR_INVALID_ARG;
   }
@@ -243,12 +282,18 @@ int server_create(const mg_server_opts *o, Server **out) {
     S->has_table = true;
   }
   S->o.table = nullptr;
+  S->lanes.resize((size_t)o->n_streams);
+  if (o->simulate) {
+    S->sched = std::thread(scheduler_loop, S);
+    for (Lane &L : S->lanes) L.waiter = std::thread(waiter_loop, S, &L);
+    *out = S;
+    return MG_OK;
+  }
   if (hipGetDevice(&S->device) != hipSuccess) {
     delete S;
     set_error("hipGetDevice failed");
     return MG_ERR_HIP;
   }
-  S->lanes.resize((size_t)o->n_streams);
   for (Lane &L : S->lanes) {
     if (hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&L.ev, hipEventDisableTiming) != hipSuccess ||

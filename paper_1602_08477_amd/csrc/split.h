@@ -17,6 +17,7 @@ struct SplitLayout {
   int64_t elem_bytes;    // 1 (INT8 slices) or 2 (BF16 slices)
   int64_t e_off, f_off;  // int32 exponents of A rows [mp], B columns [np]
   int64_t a_off, b_off;  // A slices [s][mp][kp], B slices [s][np][kp] (B transposed)
+  int64_t p_off;         // FP64 partial sums of the recombination [mp][np]
   int64_t total;         // bytes
 };
 
@@ -30,7 +31,7 @@ int split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, const d
 
 // Slice products + recombination + epilogue from a prepared workspace.
 int split_multiply(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
-                   double beta, double *C, int64_t ldc, const void *ws, hipStream_t s);
+                   double beta, double *C, int64_t ldc, void *ws, hipStream_t s);
 
 // prepare + multiply with a caller-provided workspace.
 int gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,

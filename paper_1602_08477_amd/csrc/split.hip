@@ -55,7 +55,7 @@ __global__ void fill_int_kernel(int *p, int count, int v) {
   if (i < count) p[i] = v;
 }
 
-constexpr int kColRows = 256;  // rows of B per thread in col_exp_kernel
+constexpr int kColRows = 64;  // rows of B per thread in col_exp_kernel
 
 __global__ void col_exp_kernel(const double *B, int64_t ldb, int k, int n, int *F) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -64,6 +64,7 @@ __global__ void col_exp_kernel(const double *B, int64_t ldb, int k, int n, int *
   for (int ch = blockIdx.y; ch < nchunks; ch += gridDim.y) {
     int e = INT_MIN;
     const int r1 = min(k, (ch + 1) * kColRows);
+#pragma unroll 8
     for (int r = ch * kColRows; r < r1; ++r) e = max(e, exp_of(B[(int64_t)r * ldb + j]));
     if (e != INT_MIN) atomicMax(F + j, e);
   }
@@ -118,20 +119,21 @@ __device__ __forceinline__ void slice_round(double *r, int *q, int bits) {
   }
 }
 
-// A slices, row-major [s][mp][kp]: one thread per (row, 16-byte chunk).
+// A slices, row-major [s][mp][kp]: one thread per 4 consecutive elements of
+// a row, so a wave reads 2 KB and writes 64 * 4 * ESZ bytes per slice
+// contiguously.
 template <int ESZ>
 __global__ void slice_rows_kernel(const double *A, int64_t lda, int m, int k, int mp, int64_t kp,
                                   const int *E, int s, int bits, unsigned char *out) {
-  constexpr int CW = SlicePack<ESZ>::CW;
-  const int64_t chunks_per_row = kp / CW;
+  const int64_t quads = kp / 4;
   const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (id >= (int64_t)mp * chunks_per_row) return;
-  const int i = (int)(id / chunks_per_row);
-  const int64_t c0 = (id % chunks_per_row) * CW;
+  if (id >= (int64_t)mp * quads) return;
+  const int i = (int)(id / quads);
+  const int64_t c0 = (id % quads) * 4;
   const int ei = E[i];
-  double r[CW];
+  double r[4];
 #pragma unroll
-  for (int e = 0; e < CW; ++e) {
+  for (int e = 0; e < 4; ++e) {
     const int64_t kk = c0 + e;
     const double x = (i < m && kk < k) ? A[(int64_t)i * lda + kk] : 0.0;
     r[e] = ldexp(x, -ei);
@@ -139,9 +141,18 @@ __global__ void slice_rows_kernel(const double *A, int64_t lda, int m, int k, in
   const int64_t slice_bytes = (int64_t)mp * kp * ESZ;
   unsigned char *o = out + ((int64_t)i * kp + c0) * ESZ;
   for (int t = 0; t < s; ++t) {
-    int q[CW];
-    slice_round<CW>(r, q, bits);
-    *reinterpret_cast<i4v *>(o + t * slice_bytes) = SlicePack<ESZ>::pack(q);
+    int q[4];
+    slice_round<4>(r, q, bits);
+    if (ESZ == 1) {
+      const unsigned w = (q[0] & 0xff) | ((q[1] & 0xff) << 8) | ((q[2] & 0xff) << 16) |
+                         ((unsigned)(q[3] & 0xff) << 24);
+      *reinterpret_cast<unsigned *>(o + t * slice_bytes) = w;
+    } else {
+      uint2 w;
+      w.x = SlicePack<2>::bf16_bits(q[0]) | (SlicePack<2>::bf16_bits(q[1]) << 16);
+      w.y = SlicePack<2>::bf16_bits(q[2]) | (SlicePack<2>::bf16_bits(q[3]) << 16);
+      *reinterpret_cast<uint2 *>(o + t * slice_bytes) = w;
+    }
   }
 }
 
@@ -163,7 +174,7 @@ __global__ __launch_bounds__(256) void slice_cols_kernel(const double *B, int64_
     T[kk][jj] = (gk < k && gj < n) ? B[gk * ldb + gj] : 0.0;
   }
   __syncthreads();
-  const int jj = tid & 63, kq = tid >> 6;  // column, 16-long k range
+  const int jj = tid >> 2, kq = tid & 3;  // column, 16-long k range (4 lanes per column)
   const int j = j0 + jj;
   const int fj = F[j];
   double r[16];
@@ -188,7 +199,8 @@ struct SplitMma;
 template <>
 struct SplitMma<MG_SPLIT_I8> {
   typedef i4v acc_t;
-  static constexpr int CHUNK_STAGES = 0;  // INT32 accumulates the diagonal directly
+  static constexpr int CHUNK_STAGES = 0;
+  static constexpr int MIN_BLOCKS = 2;  // two workgroups per CU fit in registers  // INT32 accumulates the diagonal directly
   __device__ static __forceinline__ acc_t mma(i4v a, i4v b, acc_t c) {
     return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
   }
@@ -197,7 +209,8 @@ struct SplitMma<MG_SPLIT_I8> {
 template <>
 struct SplitMma<MG_SPLIT_BF16> {
   typedef f4v acc_t;
-  static constexpr int CHUNK_STAGES = 4;  // 256 k: 256 * 255^2 < 2^24 keeps FP32 exact
+  static constexpr int CHUNK_STAGES = 4;
+  static constexpr int MIN_BLOCKS = 1;  // FP32 chunk + INT32 diagonal sums: one per CU  // 256 k: 256 * 255^2 < 2^24 keeps FP32 exact
   __device__ static __forceinline__ acc_t mma(i4v a, i4v b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, a),
                                                    __builtin_bit_cast(bf8v, b), c, 0, 0, 0);
@@ -207,6 +220,7 @@ struct SplitMma<MG_SPLIT_BF16> {
 struct SplitArgs {
   const unsigned char *As, *Bs;
   const int *E, *F;
+  double *P;  // FP64 partial sums [mp][np]
   double *C;
   int64_t ldc;
   int m, n, mp, np;
@@ -241,7 +255,9 @@ __device__ __forceinline__ void advance(Step &x, const SplitArgs &a) {
 constexpr int kSBM = 128, kSBN = 128;
 
 template <int ALGO>
-__global__ __launch_bounds__(256, 1) void split_gemm_kernel(SplitArgs a, int tiles_m, int tiles_n) {
+__global__ __launch_bounds__(256, SplitMma<ALGO>::MIN_BLOCKS) void split_gemm_kernel(SplitArgs a,
+                                                                                   int tiles_m,
+                                                                                   int tiles_n) {
   typedef SplitMma<ALGO> M;
   typedef typename M::acc_t Acc;
   extern __shared__ __align__(16) unsigned char lds[];
@@ -265,6 +281,8 @@ __global__ __launch_bounds__(256, 1) void split_gemm_kernel(SplitArgs a, int til
   }
   const unsigned char *abase = a.As + (int64_t)m0 * a.kp_bytes;
   const unsigned char *bbase = a.Bs + (int64_t)n0 * a.kp_bytes;
+  // This lane's partial sums in the FP64 workspace tile (padded extents).
+  double *pbase = a.P + (int64_t)(m0 + wm0 + 4 * g) * a.np + n0 + wn0 + l16;
 
   i4v ra[4], rb[4];
   auto load = [&](const Step &x) {
@@ -289,16 +307,16 @@ __global__ __launch_bounds__(256, 1) void split_gemm_kernel(SplitArgs a, int til
 
   Acc acc[4][4];
   i4v dacc[4][4];  // BF16 only: exact INT32 diagonal sum of FP32 chunk results
-  double facc[4][4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       acc[i][j] = Acc{};
       dacc[i][j] = i4v{};
-#pragma unroll
-      for (int r = 0; r < 4; ++r) facc[i][j][r] = 0.0;
     }
+  auto diag_value = [&](int i, int j, int r) -> int {
+    return M::CHUNK_STAGES > 0 ? dacc[i][j][r] : (int)acc[i][j][r];
+  };
 
   const int pairs = a.s * (a.s + 1) / 2;
   const int T = pairs * a.total_stages;
@@ -339,16 +357,21 @@ __global__ __launch_bounds__(256, 1) void split_gemm_kernel(SplitArgs a, int til
             acc[i][j][r] = 0;
           }
     }
-    if (seg_last && cur.p == pmax_of(cur.d, a.s)) {
+    // End of a diagonal (within a k segment), except the very last step:
+    // fold P_d * 2^(-b d) into this lane's FP64 partial sums.  Each lane only
+    // ever touches its own partial-sum addresses, so program order suffices.
+    if (t + 1 < T && seg_last && cur.p == pmax_of(cur.d, a.s)) {
       const double sc = ldexp(1.0, -a.bits * cur.d);
+      const bool first = cur.seg == 0 && cur.d == 2;
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int v = M::CHUNK_STAGES > 0 ? dacc[i][j][r] : (int)acc[i][j][r];
-            facc[i][j][r] = fma((double)v, sc, facc[i][j][r]);
+            double *pp = pbase + (int64_t)(16 * i + r) * a.np + 16 * j;
+            const double part = first ? 0.0 : *pp;
+            *pp = fma((double)diag_value(i, j, r), sc, part);
             dacc[i][j][r] = 0;
             if (M::CHUNK_STAGES == 0) acc[i][j][r] = 0;
           }
@@ -358,19 +381,23 @@ __global__ __launch_bounds__(256, 1) void split_gemm_kernel(SplitArgs a, int til
     cur = nxt;
   }
 
-  // Epilogue: C = alpha * 2^(E_i + F_j) * acc + beta * C, rounded as written.
+  // Last diagonal of the last segment, then the epilogue:
+  // C = alpha * 2^(E_i + F_j) * acc + beta * C, rounded as written.
+  const double sc = ldexp(1.0, -a.bits * (a.s + 1));
+  const bool only = a.s == 1 && a.seg_stages >= a.total_stages;  // a single fold in all
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int col = n0 + wn0 + 16 * j + l16;
-      if (col >= a.n) continue;
-      const int fj = a.F[col];
+      const int fj = col < a.n ? a.F[col] : 0;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm0 + 16 * i + 4 * g + r;
-        if (row >= a.m) continue;
-        const double prod = ldexp(facc[i][j][r], a.E[row] + fj);
+        const double part = only ? 0.0 : pbase[(int64_t)(16 * i + r) * a.np + 16 * j];
+        const double fin = fma((double)diag_value(i, j, r), sc, part);
+        if (row >= a.m || col >= a.n) continue;
+        const double prod = ldexp(fin, a.E[row] + fj);
         double *pc = a.C + (int64_t)row * a.ldc + col;
         double o = __dmul_rn(a.alpha, prod);
         if (a.beta != 0.0) o = __dadd_rn(o, __dmul_rn(a.beta, *pc));
@@ -418,6 +445,8 @@ int split_layout(int algo, int slices, int64_t m, int64_t n, int64_t k, SplitLay
   off = round_up(off + slices * L->mp * L->kp * L->elem_bytes, 256);
   L->b_off = off;
   off = round_up(off + slices * L->np * L->kp * L->elem_bytes, 256);
+  L->p_off = off;
+  off = round_up(off + 8 * L->mp * L->np, 256);
   L->total = off;
   return MG_OK;
 }
@@ -448,8 +477,7 @@ int split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, const d
   MG_HIP_TRY(hipGetLastError());
 
   unsigned char *As = w + L.a_off, *Bs = w + L.b_off;
-  const int64_t cw = algo == MG_SPLIT_BF16 ? 8 : 16;
-  const int64_t rthreads = L.mp * (L.kp / cw);
+  const int64_t rthreads = L.mp * (L.kp / 4);
   const int64_t cblocks = (L.np / 64) * (L.kp / 64);
   if (rthreads / 256 + 1 > INT32_MAX || cblocks > INT32_MAX) {
     set_error("split operands too large");
@@ -471,12 +499,13 @@ int split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, const d
 }
 
 int split_multiply(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
-                   double beta, double *C, int64_t ldc, const void *ws, hipStream_t s) {
+                   double beta, double *C, int64_t ldc, void *ws, hipStream_t s) {
   SplitLayout L;
   int rc = split_layout(algo, slices, m, n, k, &L);
   if (rc != MG_OK) return rc;
-  const unsigned char *w = static_cast<const unsigned char *>(ws);
+  unsigned char *w = static_cast<unsigned char *>(ws);
   SplitArgs a;
+  a.P = reinterpret_cast<double *>(w + L.p_off);
   a.As = w + L.a_off;
   a.Bs = w + L.b_off;
   a.E = reinterpret_cast<const int *>(w + L.e_off);

@@ -328,6 +328,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--quick", action="store_true", help="headline only (for profiling)")
+    ap.add_argument("--leg", choices=["split", "batched", "serving"], default=None,
+                    help="run only this secondary leg and print its record (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--copy-gib", type=float, default=0.0,
@@ -345,6 +347,12 @@ def main():
     if not torch.cuda.is_available():
         eprint("no GPU visible")
         sys.exit(3)
+    if args.leg is not None:
+        fn = {"split": lambda: bench_split(4096, max(3, args.steps), 1),
+              "batched": lambda: bench_batched(max(3, args.steps)),
+              "serving": lambda: bench_serving(args.serve_seconds)}[args.leg]
+        print(json.dumps({"leg": args.leg, "record": fn()}), flush=True)
+        return
     n = args.n
     eprint(f"bench: native FP64 n={n} steps={args.steps} warmup={args.warmup}")
     ms_step, kern_ms, err = bench_native(n, args.steps, args.warmup)

@@ -115,7 +115,7 @@ int mg_pick_tile_cfg(int dtype, int64_t m, int64_t n, int64_t k);
  * element by |alpha| k 2^(E_i+F_j) (s+3) 2^(-b s) plus FP64 rounding.
  *
  * Workspace layout (bytes from the workspace base; all offsets 256-aligned):
- *   mp, np, kp = m, n, k rounded up to 128 (at least 128)
+ *   mp, np = m, n rounded up to 256; kp = k rounded up to 128 (all >= 1)
  *   int32 E[mp] at e_off, int32 F[np] at f_off (padding entries 0)
  *   A slices at a_off: [s][mp][kp] row-major elements (INT8, or BF16 bits)
  *   B slices at b_off: [s][np][kp], i.e. slice t of B transposed (k fastest)
@@ -146,6 +146,19 @@ int mg_gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double 
                   double *C, int64_t ldc, void *workspace, int64_t workspace_bytes,
                   void *stream);
 
+/* Work divisions of the slice-product kernel (all give identical bits):
+ * 0: 128x128 tile on 4 wavefronts, register-staged double buffer;
+ * with a ring of direct-to-LDS stages: 1: 128x128 on 4 (ring of 4),
+ * 2: 128x256 on 8 (ring of 3), 3: 256x128 on 4 (ring of 3), 4: 256x256 on
+ * 16 (ring of 2), 5: 128x256 on 8 (ring of 2).  mg_gemm_split picks by size;
+ * mg_gemm_split_cfg takes cfg explicitly (-1 = pick).  MG_ERR_INVALID_ARG for
+ * an unknown cfg. */
+int mg_split_num_cfgs(void);
+int mg_gemm_split_cfg(int algo, int slices, int cfg, int64_t m, int64_t n, int64_t k,
+                      double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                      double beta, double *C, int64_t ldc, void *workspace,
+                      int64_t workspace_bytes, void *stream);
+
 /* ------------------------------------------------------- batched GEMM --
  * Many independent problems C_i <- alpha_i A_i B_i + beta_i C_i (each the
  * Section 4.2 operation) in ONE persistent launch.  A plan validates the
@@ -170,7 +183,7 @@ typedef struct mg_problem {
   int64_t ldc;
 } mg_problem;
 
-#define MG_NUM_GROUPED_CLASSES 3 /* tile classes: 128x64, 64x64, 32x32   */
+#define MG_NUM_GROUPED_CLASSES 3 /* tile classes: 64x64, 64x32, 32x32    */
 #define MG_TUNE_EDGES 6          /* per-extent buckets, see mg_tune_bucket */
 #define MG_TUNE_BUCKETS 216      /* MG_TUNE_EDGES^3                        */
 

@@ -76,6 +76,8 @@ def lib() -> ctypes.CDLL:
                                        _i64, _vp]
         L.mg_gemm_split.argtypes = [_int, _int, _i64, _i64, _i64, _dbl, _vp, _i64, _vp, _i64,
                                     _dbl, _vp, _i64, _vp, _i64, _vp]
+        L.mg_gemm_split_cfg.argtypes = [_int, _int, _int, _i64, _i64, _i64, _dbl, _vp, _i64, _vp,
+                                        _i64, _dbl, _vp, _i64, _vp, _i64, _vp]
         _bind_batched(L)
         _bind_server(L)
         _lib = L
@@ -194,17 +196,22 @@ def split_prepare(algo: int, slices: int, A, B, workspace, stream=None):
     return workspace
 
 
+def split_num_cfgs() -> int:
+    return lib().mg_split_num_cfgs()
+
+
 def gemm_split(A, B, C, alpha: float = 1.0, beta: float = 0.0, algo: int = SPLIT_I8,
-               slices: int | None = None, workspace=None, stream=None):
-    """C <- alpha*A@B + beta*C through the split-precision path (mg_gemm_split)."""
+               slices: int | None = None, workspace=None, stream=None, cfg: int = -1):
+    """C <- alpha*A@B + beta*C through the split-precision path
+    (mg_gemm_split_cfg; cfg -1 lets the library pick the work division)."""
     (pa, lda), (pb, ldb), (pc, ldc), m, n, k = _mnk(A, B, C, None)
     if slices is None:
         slices = split_default_slices(algo)
     if workspace is None:
         workspace = split_workspace(algo, slices, m, n, k, device=C.device)
-    check(lib().mg_gemm_split(algo, slices, m, n, k, alpha, pa, lda, pb, ldb, beta, pc, ldc,
-                              ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
-                              _stream_handle(stream)))
+    check(lib().mg_gemm_split_cfg(algo, slices, cfg, m, n, k, alpha, pa, lda, pb, ldb, beta, pc,
+                                  ldc, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                  _stream_handle(stream)))
     return C
 
 

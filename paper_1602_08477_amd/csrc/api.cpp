@@ -295,11 +295,17 @@ int mg_split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, cons
                        static_cast<hipStream_t>(stream));
 }
 
-int mg_gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
-                  const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
-                  double *C, int64_t ldc, void *workspace, int64_t workspace_bytes,
-                  void *stream) {
+int mg_split_num_cfgs(void) { return split_num_cfgs(); }
+
+int mg_gemm_split_cfg(int algo, int slices, int cfg, int64_t m, int64_t n, int64_t k,
+                      double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                      double beta, double *C, int64_t ldc, void *workspace,
+                      int64_t workspace_bytes, void *stream) {
   clear_error();
+  if (cfg < -1 || cfg >= split_num_cfgs()) {
+    set_error("unknown split cfg %d", cfg);
+    return MG_ERR_INVALID_ARG;
+  }
   SplitLayout L;
   int rc = split_layout(algo, slices, m, n, k, &L);
   if (rc != MG_OK) return rc;
@@ -323,7 +329,15 @@ int mg_gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double 
     }
   }
   return gemm_split(algo, slices, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, workspace,
-                    workspace_bytes, static_cast<hipStream_t>(stream));
+                    workspace_bytes, static_cast<hipStream_t>(stream), cfg);
+}
+
+int mg_gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
+                  const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+                  double *C, int64_t ldc, void *workspace, int64_t workspace_bytes,
+                  void *stream) {
+  return mg_gemm_split_cfg(algo, slices, -1, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                           workspace, workspace_bytes, stream);
 }
 
 int mg_grouped_class_info(int cls, int *bm, int *bn) {

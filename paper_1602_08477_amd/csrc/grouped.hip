@@ -29,8 +29,8 @@ namespace mg {
 namespace {
 
 // Tile classes of the persistent kernel (work divisions per problem).
-constexpr int kClsBM[kNumGroupedClasses] = {128, 64, 32};
-constexpr int kClsBN[kNumGroupedClasses] = {64, 64, 32};
+constexpr int kClsBM[kNumGroupedClasses] = {64, 64, 32};
+constexpr int kClsBN[kNumGroupedClasses] = {64, 32, 32};
 constexpr int kScaleCls = 15;  // C <- beta*C only (alpha == 0 or k == 0)
 constexpr int kScaleTile = 64;
 
@@ -56,30 +56,33 @@ __device__ __forceinline__ void scale_tile(const GemmArgs<T> &g, int m0, int n0)
   }
 }
 
+// Persistent loop.  Thread 0 fetches the next tile index while the
+// workgroup computes the current one, so the atomic's latency is hidden; the
+// barriers inside gemm_tile order its write before the read after the tile.
 template <typename T>
-__global__ __launch_bounds__(kTileThreads, 2) void grouped_kernel(const GProb<T> *__restrict__ probs,
+__global__ __launch_bounds__(kTileThreads, 3) void grouped_kernel(const GProb<T> *__restrict__ probs,
                                                                   const GTile *__restrict__ tiles,
                                                                   int ntiles, int *counter) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int s_next;
   T *smem = reinterpret_cast<T *>(lds_raw);
-  for (;;) {
+  if (threadIdx.x == 0) s_next = atomicAdd(counter, 1);
+  __syncthreads();
+  int w = s_next;
+  __syncthreads();
+  while (w < ntiles) {
     if (threadIdx.x == 0) s_next = atomicAdd(counter, 1);
-    __syncthreads();
-    const int w = s_next;
-    __syncthreads();
-    if (w >= ntiles) break;
     const GTile t = tiles[w];
     const GemmArgs<T> g = probs[t.prob].g;
     const bool vec = (t.cls >> 4) & 1;
     switch (t.cls & 15) {
       case 0:
-        if (vec) gemm_tile<T, 128, 64, true>(g, t.tm * 128, t.tn * 64, smem);
-        else gemm_tile<T, 128, 64, false>(g, t.tm * 128, t.tn * 64, smem);
-        break;
-      case 1:
         if (vec) gemm_tile<T, 64, 64, true>(g, t.tm * 64, t.tn * 64, smem);
         else gemm_tile<T, 64, 64, false>(g, t.tm * 64, t.tn * 64, smem);
+        break;
+      case 1:
+        if (vec) gemm_tile<T, 64, 32, true>(g, t.tm * 64, t.tn * 32, smem);
+        else gemm_tile<T, 64, 32, false>(g, t.tm * 64, t.tn * 32, smem);
         break;
       case 2:
         if (vec) gemm_tile<T, 32, 32, true>(g, t.tm * 32, t.tn * 32, smem);
@@ -89,6 +92,9 @@ __global__ __launch_bounds__(kTileThreads, 2) void grouped_kernel(const GProb<T>
         scale_tile<T>(g, t.tm * kScaleTile, t.tn * kScaleTile);
         break;
     }
+    __syncthreads();
+    w = s_next;
+    __syncthreads();
   }
 }
 
@@ -98,7 +104,7 @@ __global__ void reset_counter_kernel(int *counter) {
 
 template <typename T>
 size_t grouped_lds_bytes() {
-  return std::max({TileShape<T, 128, 64>::LDS_BYTES, TileShape<T, 64, 64>::LDS_BYTES,
+  return std::max({TileShape<T, 64, 64>::LDS_BYTES, TileShape<T, 64, 32>::LDS_BYTES,
                    TileShape<T, 32, 32>::LDS_BYTES});
 }
 

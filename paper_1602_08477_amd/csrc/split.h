@@ -8,8 +8,10 @@
 
 namespace mg {
 
-// Padding granularity of the workspace copies (rows of A, columns of B, k).
-constexpr int kSplitTile = 128;
+// Padding granularity of the workspace copies: rows of A and columns of B
+// (the largest product tile), and k (one LDS stage).
+constexpr int kSplitTileMN = 256;
+constexpr int kSplitTileK = 128;
 constexpr int kSplitMaxSlices = 16;
 
 struct SplitLayout {
@@ -29,14 +31,18 @@ int split_layout(int algo, int slices, int64_t m, int64_t n, int64_t k, SplitLay
 int split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, const double *A,
                   int64_t lda, const double *B, int64_t ldb, void *ws, hipStream_t s);
 
+// Work divisions of the product kernel; cfg < 0 picks by size.
+int split_num_cfgs();
+int split_pick_cfg(int64_t mp, int64_t np);
+
 // Slice products + recombination + epilogue from a prepared workspace.
 int split_multiply(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
-                   double beta, double *C, int64_t ldc, void *ws, hipStream_t s);
+                   double beta, double *C, int64_t ldc, void *ws, hipStream_t s, int cfg = -1);
 
 // prepare + multiply with a caller-provided workspace.
 int gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
                const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
-               double *C, int64_t ldc, void *ws, int64_t ws_bytes, hipStream_t s);
+               double *C, int64_t ldc, void *ws, int64_t ws_bytes, hipStream_t s, int cfg = -1);
 
 // The same with a workspace from HIP's stream-ordered allocator on `s`.
 int gemm_split_pooled(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,

@@ -199,8 +199,7 @@ struct SplitMma;
 template <>
 struct SplitMma<MG_SPLIT_I8> {
   typedef i4v acc_t;
-  static constexpr int CHUNK_STAGES = 0;
-  static constexpr int MIN_BLOCKS = 2;  // two workgroups per CU fit in registers  // INT32 accumulates the diagonal directly
+  static constexpr int CHUNK_STAGES = 0;  // INT32 accumulates a diagonal directly
   __device__ static __forceinline__ acc_t mma(i4v a, i4v b, acc_t c) {
     return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
   }
@@ -209,8 +208,7 @@ struct SplitMma<MG_SPLIT_I8> {
 template <>
 struct SplitMma<MG_SPLIT_BF16> {
   typedef f4v acc_t;
-  static constexpr int CHUNK_STAGES = 4;
-  static constexpr int MIN_BLOCKS = 1;  // FP32 chunk + INT32 diagonal sums: one per CU  // 256 k: 256 * 255^2 < 2^24 keeps FP32 exact
+  static constexpr int CHUNK_STAGES = 4;  // 256 k: 256 * 255^2 < 2^24 keeps FP32 exact
   __device__ static __forceinline__ acc_t mma(i4v a, i4v b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, a),
                                                    __builtin_bit_cast(bf8v, b), c, 0, 0, 0);
@@ -252,71 +250,147 @@ __device__ __forceinline__ void advance(Step &x, const SplitArgs &a) {
   x.p = max(1, x.d - a.s);
 }
 
-constexpr int kSBM = 128, kSBN = 128;
+// Partial sums of step 4 live in the workspace tile-major and lane-contiguous:
+// element e of lane t of tile b at P[b*BM*BN + e*THREADS + t], so each
+// fold reads and writes whole contiguous rows of lanes with constant offsets.
+// Element e = (i*FNW + j)*4 + r is output row 16i + 4g + r, column 16j + l16
+// of the wave's sub-tile (g = lane/16, l16 = lane%16).
+template <typename M, int FMW, int FNW, int THREADS>
+__device__ __forceinline__ void fold_partials(typename M::acc_t (&acc)[FMW][FNW],
+                                              i4v (&dacc)[FMW][FNW], double *plane, double sc,
+                                              bool first) {
+#pragma unroll
+  for (int i = 0; i < FMW; ++i) {
+#pragma unroll
+    for (int j = 0; j < FNW; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double *pp = plane + ((i * FNW + j) * 4 + r) * THREADS;
+        const int v = M::CHUNK_STAGES > 0 ? dacc[i][j][r] : (int)acc[i][j][r];
+        const double part = first ? 0.0 : *pp;
+        *pp = fma((double)v, sc, part);
+        dacc[i][j][r] = 0;
+        if (M::CHUNK_STAGES == 0) acc[i][j][r] = 0;
+      }
+    // keep one row of blocks in flight: bounds the live FP64 registers
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
 
-template <int ALGO>
-__global__ __launch_bounds__(256, SplitMma<ALGO>::MIN_BLOCKS) void split_gemm_kernel(SplitArgs a,
-                                                                                   int tiles_m,
-                                                                                   int tiles_n) {
+// Last fold, then C = alpha * 2^(E_i + F_j) * acc + beta * C, each product and
+// the sum rounded once.  (row0, col0): this lane's first output.
+template <typename M, int FMW, int FNW, int THREADS>
+__device__ __forceinline__ void finish_tile(const SplitArgs &a, typename M::acc_t (&acc)[FMW][FNW],
+                                            i4v (&dacc)[FMW][FNW], const double *plane,
+                                            bool only, int row0, int col0) {
+  const double sc = ldexp(1.0, -a.bits * (a.s + 1));
+#pragma unroll
+  for (int i = 0; i < FMW; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row0 + 16 * i + r;
+      const bool row_ok = row < a.m;
+      const int er = row_ok ? a.E[row] : 0;
+      double *crow = a.C + (int64_t)(row_ok ? row : 0) * a.ldc;
+#pragma unroll
+      for (int j = 0; j < FNW; ++j) {
+        const int col = col0 + 16 * j;
+        const int v = M::CHUNK_STAGES > 0 ? dacc[i][j][r] : (int)acc[i][j][r];
+        const double part = only ? 0.0 : plane[((i * FNW + j) * 4 + r) * THREADS];
+        const double fin = fma((double)v, sc, part);
+        if (!row_ok || col >= a.n) continue;
+        const double prod = ldexp(fin, er + a.F[col]);
+        double o = __dmul_rn(a.alpha, prod);
+        if (a.beta != 0.0) o = __dadd_rn(o, __dmul_rn(a.beta, crow[col]));
+        crow[col] = o;
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Work divisions of the product kernel: WGM x WGN wavefronts, each owning
+// FMW x FNW blocks of 16x16 outputs.
+template <int WGM, int WGN, int FMW, int FNW>
+struct SplitShape {
+  static constexpr int THREADS = 64 * WGM * WGN;
+  static constexpr int BM = WGM * 16 * FMW, BN = WGN * 16 * FNW;
+  static constexpr int STAGE = (BM + BN) * kPitch;  // bytes of one LDS stage
+  static constexpr size_t LDS_BYTES = 2 * (size_t)STAGE;
+  static constexpr int NA = BM * (kStageBytes / 16) / THREADS;  // 16-byte chunks per thread
+  static constexpr int NB = BN * (kStageBytes / 16) / THREADS;
+  static_assert(NA * THREADS == BM * (kStageBytes / 16) && NB * THREADS == BN * (kStageBytes / 16),
+                "whole chunks per thread");
+};
+
+template <int ALGO, int WGM, int WGN, int FMW, int FNW, int MINB>
+__global__ __launch_bounds__((SplitShape<WGM, WGN, FMW, FNW>::THREADS), MINB) void split_gemm_kernel(
+    SplitArgs a, int tiles_m, int tiles_n) {
   typedef SplitMma<ALGO> M;
   typedef typename M::acc_t Acc;
+  typedef SplitShape<WGM, WGN, FMW, FNW> S;
+  constexpr int BM = S::BM, BN = S::BN, STAGE = S::STAGE;
+  constexpr int CPR = kStageBytes / 16;  // 16-byte chunks per slice row and stage
   extern __shared__ __align__(16) unsigned char lds[];
-  constexpr int STAGE = (kSBM + kSBN) * kPitch;
 
   int tm, tn;
   grouped_tile(xcd_remap(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, tm, tn);
-  const int m0 = tm * kSBM, n0 = tn * kSBN;
+  const int m0 = tm * BM, n0 = tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
+  const int wm0 = (wave / WGN) * 16 * FMW, wn0 = (wave % WGN) * 16 * FNW;
   const int g = lane >> 4, l16 = lane & 15;
 
   const int64_t a_slice = (int64_t)a.mp * a.kp_bytes, b_slice = (int64_t)a.np * a.kp_bytes;
-  // 16-byte chunk q = tid + 256u of a 128-row x 128-byte stage: row q/8, byte (q%8)*16.
-  int lrow[4], lcol[4];
+  // 16-byte chunk q = tid + THREADS*u of a stage: row q / CPR, byte (q % CPR) * 16.
+  int arow[S::NA], acol[S::NA], brow[S::NB], bcol[S::NB];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int q = tid + 256 * u;
-    lrow[u] = q >> 3;
-    lcol[u] = (q & 7) * 16;
+  for (int u = 0; u < S::NA; ++u) {
+    const int q = tid + S::THREADS * u;
+    arow[u] = q / CPR;
+    acol[u] = (q % CPR) * 16;
+  }
+#pragma unroll
+  for (int u = 0; u < S::NB; ++u) {
+    const int q = tid + S::THREADS * u;
+    brow[u] = q / CPR;
+    bcol[u] = (q % CPR) * 16;
   }
   const unsigned char *abase = a.As + (int64_t)m0 * a.kp_bytes;
   const unsigned char *bbase = a.Bs + (int64_t)n0 * a.kp_bytes;
-  // This lane's partial sums in the FP64 workspace tile (padded extents).
-  double *pbase = a.P + (int64_t)(m0 + wm0 + 4 * g) * a.np + n0 + wn0 + l16;
+  double *plane = a.P + (int64_t)blockIdx.x * (BM * BN) + tid;  // this lane's partial sums
 
-  i4v ra[4], rb[4];
+  i4v ra[S::NA], rb[S::NB];
   auto load = [&](const Step &x) {
     const int64_t koff = (int64_t)(x.seg * a.seg_stages + x.st) * kStageBytes;
     const unsigned char *pa = abase + (x.p - 1) * a_slice + koff;
     const unsigned char *pb = bbase + (x.d - x.p - 1) * b_slice + koff;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      ra[u] = *reinterpret_cast<const i4v *>(pa + lrow[u] * a.kp_bytes + lcol[u]);
-      rb[u] = *reinterpret_cast<const i4v *>(pb + lrow[u] * a.kp_bytes + lcol[u]);
-    }
+    for (int u = 0; u < S::NA; ++u)
+      ra[u] = *reinterpret_cast<const i4v *>(pa + arow[u] * a.kp_bytes + acol[u]);
+#pragma unroll
+    for (int u = 0; u < S::NB; ++u)
+      rb[u] = *reinterpret_cast<const i4v *>(pb + brow[u] * a.kp_bytes + bcol[u]);
   };
   auto store = [&](int stage) {
     unsigned char *As = lds + stage * STAGE;
-    unsigned char *Bs = As + kSBM * kPitch;
+    unsigned char *Bs = As + BM * kPitch;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      *reinterpret_cast<i4v *>(As + lrow[u] * kPitch + lcol[u]) = ra[u];
-      *reinterpret_cast<i4v *>(Bs + lrow[u] * kPitch + lcol[u]) = rb[u];
-    }
+    for (int u = 0; u < S::NA; ++u)
+      *reinterpret_cast<i4v *>(As + arow[u] * kPitch + acol[u]) = ra[u];
+#pragma unroll
+    for (int u = 0; u < S::NB; ++u)
+      *reinterpret_cast<i4v *>(Bs + brow[u] * kPitch + bcol[u]) = rb[u];
   };
 
-  Acc acc[4][4];
-  i4v dacc[4][4];  // BF16 only: exact INT32 diagonal sum of FP32 chunk results
+  Acc acc[FMW][FNW];
+  i4v dacc[FMW][FNW];  // BF16 only: exact INT32 diagonal sum of FP32 chunk results
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FMW; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < FNW; ++j) {
       acc[i][j] = Acc{};
       dacc[i][j] = i4v{};
     }
-  auto diag_value = [&](int i, int j, int r) -> int {
-    return M::CHUNK_STAGES > 0 ? dacc[i][j][r] : (int)acc[i][j][r];
-  };
 
   const int pairs = a.s * (a.s + 1) / 2;
   const int T = pairs * a.total_stages;
@@ -329,28 +403,28 @@ __global__ __launch_bounds__(256, SplitMma<ALGO>::MIN_BLOCKS) void split_gemm_ke
     advance(nxt, a);
     if (t + 1 < T) load(nxt);
     const unsigned char *As = lds + (t & 1) * STAGE;
-    const unsigned char *Bs = As + kSBM * kPitch;
+    const unsigned char *Bs = As + BM * kPitch;
 #pragma unroll
     for (int h = 0; h < kStageBytes / 64; ++h) {
-      i4v fa[4], fb[4];
+      i4v fa[FMW], fb[FNW];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < FMW; ++i)
         fa[i] = *reinterpret_cast<const i4v *>(As + (wm0 + 16 * i + l16) * kPitch + h * 64 + g * 16);
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < FNW; ++j)
         fb[j] = *reinterpret_cast<const i4v *>(Bs + (wn0 + 16 * j + l16) * kPitch + h * 64 + g * 16);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < FMW; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = M::mma(fa[i], fb[j], acc[i][j]);
+        for (int j = 0; j < FNW; ++j) acc[i][j] = M::mma(fa[i], fb[j], acc[i][j]);
     }
     const bool seg_last = cur.st + 1 == seg_len(cur.seg, a);
     if (M::CHUNK_STAGES > 0 && ((cur.st + 1) % (M::CHUNK_STAGES > 0 ? M::CHUNK_STAGES : 1) == 0 ||
                                 seg_last)) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < FMW; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < FNW; ++j)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             dacc[i][j][r] += (int)acc[i][j][r];
@@ -360,50 +434,179 @@ __global__ __launch_bounds__(256, SplitMma<ALGO>::MIN_BLOCKS) void split_gemm_ke
     // End of a diagonal (within a k segment), except the very last step:
     // fold P_d * 2^(-b d) into this lane's FP64 partial sums.  Each lane only
     // ever touches its own partial-sum addresses, so program order suffices.
-    if (t + 1 < T && seg_last && cur.p == pmax_of(cur.d, a.s)) {
-      const double sc = ldexp(1.0, -a.bits * cur.d);
-      const bool first = cur.seg == 0 && cur.d == 2;
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            double *pp = pbase + (int64_t)(16 * i + r) * a.np + 16 * j;
-            const double part = first ? 0.0 : *pp;
-            *pp = fma((double)diag_value(i, j, r), sc, part);
-            dacc[i][j][r] = 0;
-            if (M::CHUNK_STAGES == 0) acc[i][j][r] = 0;
-          }
-    }
+    if (t + 1 < T && seg_last && cur.p == pmax_of(cur.d, a.s))
+      fold_partials<M, FMW, FNW, S::THREADS>(acc, dacc, plane, ldexp(1.0, -a.bits * cur.d),
+                                             cur.seg == 0 && cur.d == 2);
     if (t + 1 < T) store((t + 1) & 1);
     __syncthreads();
     cur = nxt;
   }
 
-  // Last diagonal of the last segment, then the epilogue:
-  // C = alpha * 2^(E_i + F_j) * acc + beta * C, rounded as written.
-  const double sc = ldexp(1.0, -a.bits * (a.s + 1));
+  // Last diagonal of the last segment, then the epilogue.
   const bool only = a.s == 1 && a.seg_stages >= a.total_stages;  // a single fold in all
+  finish_tile<M, FMW, FNW, S::THREADS>(a, acc, dacc, plane, only, m0 + wm0 + 4 * g,
+                                       n0 + wn0 + l16);
+}
+
+// ---------------------------------------------------------------------------
+// Variant with direct global->LDS loads (gfx950 global_load_lds_dwordx4) into
+// an NS-stage ring, so NS-1 stages of slice data are in flight while the
+// matrix cores work on the current one, without staging registers.
+// LDS rows are 128 bytes without padding; the 16-byte chunk c of row r is
+// stored at chunk c ^ ((r >> 1) & 7), which keeps both the DMA writes
+// (1 KB contiguous per wave instruction) and the fragment reads (16 rows,
+// one chunk each) free of bank conflicts.
+template <int WGM, int WGN, int FMW, int FNW, int NS>
+struct SplitDmaShape {
+  static constexpr int THREADS = 64 * WGM * WGN;
+  static constexpr int WAVES = WGM * WGN;
+  static constexpr int BM = WGM * 16 * FMW, BN = WGN * 16 * FNW;
+  static constexpr int STAGE = (BM + BN) * kStageBytes;  // bytes
+  static constexpr size_t LDS_BYTES = (size_t)NS * STAGE;
+  static constexpr int IA = BM / 8 / WAVES;  // DMA instructions (8 rows each) per wave, A
+  static constexpr int IB = BN / 8 / WAVES;
+  static_assert(IA * 8 * WAVES == BM && IB * 8 * WAVES == BN, "whole DMA rows per wave");
+  static_assert(NS >= 2, "at least double buffering");
+};
+
+__device__ __forceinline__ int swz_chunk(int row, int chunk) { return chunk ^ ((row >> 1) & 7); }
+
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  // gfx9 s_waitcnt encoding: vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt[15:14]
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// One 16-byte-per-lane direct load: lane l's chunk lands at lds_row_block + 16*l.
+__device__ __forceinline__ void dma16(const unsigned char *src, unsigned char *lds_dst) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds_dst, 16, 0,
+                                   0);
+}
+
+template <int ALGO, int WGM, int WGN, int FMW, int FNW, int NS>
+__global__ __launch_bounds__((SplitDmaShape<WGM, WGN, FMW, FNW, NS>::THREADS), 1) void
+split_gemm_dma_kernel(SplitArgs a, int tiles_m, int tiles_n) {
+  typedef SplitMma<ALGO> M;
+  typedef typename M::acc_t Acc;
+  typedef SplitDmaShape<WGM, WGN, FMW, FNW, NS> S;
+  constexpr int BM = S::BM, BN = S::BN, STAGE = S::STAGE;
+  constexpr int DPS = S::IA + S::IB;  // DMA instructions per step per wave
+  extern __shared__ __align__(16) unsigned char lds[];
+
+  int tm, tn;
+  grouped_tile(xcd_remap(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, tm, tn);
+  const int m0 = tm * BM, n0 = tn * S::BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave / WGN) * 16 * FMW, wn0 = (wave % WGN) * 16 * FNW;
+  const int g = lane >> 4, l16 = lane & 15;
+
+  const int64_t a_slice = (int64_t)a.mp * a.kp_bytes, b_slice = (int64_t)a.np * a.kp_bytes;
+  // DMA source offsets of this lane: instruction u covers rows 8*(wave*I + u) .. +7;
+  // the lane supplies row +lane/8, physical chunk lane%8 = logical swz_chunk(row, lane%8).
+  int64_t asrc[S::IA], bsrc[S::IB];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int u = 0; u < S::IA; ++u) {
+    const int row = 8 * (wave * S::IA + u) + (lane >> 3);
+    asrc[u] = (int64_t)(m0 + row) * a.kp_bytes + swz_chunk(row, lane & 7) * 16;
+  }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int col = n0 + wn0 + 16 * j + l16;
-      const int fj = col < a.n ? a.F[col] : 0;
+  for (int u = 0; u < S::IB; ++u) {
+    const int row = 8 * (wave * S::IB + u) + (lane >> 3);
+    bsrc[u] = (int64_t)(n0 + row) * a.kp_bytes + swz_chunk(row, lane & 7) * 16;
+  }
+  double *plane = a.P + (int64_t)blockIdx.x * (BM * BN) + tid;  // this lane's partial sums
+
+  auto issue = [&](const Step &x, int stage) {
+    const int64_t koff = (int64_t)(x.seg * a.seg_stages + x.st) * kStageBytes;
+    const unsigned char *pa = a.As + (x.p - 1) * a_slice + koff;
+    const unsigned char *pb = a.Bs + (x.d - x.p - 1) * b_slice + koff;
+    unsigned char *la = lds + stage * STAGE;
+    unsigned char *lb = la + BM * kStageBytes;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm0 + 16 * i + 4 * g + r;
-        const double part = only ? 0.0 : pbase[(int64_t)(16 * i + r) * a.np + 16 * j];
-        const double fin = fma((double)diag_value(i, j, r), sc, part);
-        if (row >= a.m || col >= a.n) continue;
-        const double prod = ldexp(fin, a.E[row] + fj);
-        double *pc = a.C + (int64_t)row * a.ldc + col;
-        double o = __dmul_rn(a.alpha, prod);
-        if (a.beta != 0.0) o = __dadd_rn(o, __dmul_rn(a.beta, *pc));
-        *pc = o;
-      }
+    for (int u = 0; u < S::IA; ++u)
+      dma16(pa + asrc[u], la + (wave * S::IA + u) * 8 * kStageBytes);
+#pragma unroll
+    for (int u = 0; u < S::IB; ++u)
+      dma16(pb + bsrc[u], lb + (wave * S::IB + u) * 8 * kStageBytes);
+  };
+
+  Acc acc[FMW][FNW];
+  i4v dacc[FMW][FNW];
+#pragma unroll
+  for (int i = 0; i < FMW; ++i)
+#pragma unroll
+    for (int j = 0; j < FNW; ++j) {
+      acc[i][j] = Acc{};
+      dacc[i][j] = i4v{};
     }
+
+  const int pairs = a.s * (a.s + 1) / 2;
+  const int T = pairs * a.total_stages;
+  Step cur = {0, 2, 1, 0};
+  Step ld = cur;
+  // prologue: steps 0 .. NS-2
+#pragma unroll
+  for (int q = 0; q < NS - 1; ++q) {
+    if (q < T) {
+      issue(ld, q);
+      advance(ld, a);
+    }
+  }
+  for (int t = 0; t < T; ++t) {
+    // step t landed when at most the later steps' DMAs are outstanding
+    if (t + NS - 2 < T) wait_vmcnt<(NS - 2) * DPS>();
+    else wait_vmcnt<0>();
+    __builtin_amdgcn_s_barrier();
+    if (t + NS - 1 < T) {
+      issue(ld, (t + NS - 1) % NS);
+      advance(ld, a);
+    }
+    const unsigned char *As = lds + (t % NS) * STAGE;
+    const unsigned char *Bs = As + BM * kStageBytes;
+#pragma unroll
+    for (int h = 0; h < kStageBytes / 64; ++h) {
+      i4v fa[FMW], fb[FNW];
+#pragma unroll
+      for (int i = 0; i < FMW; ++i) {
+        const int row = wm0 + 16 * i + l16;
+        fa[i] = *reinterpret_cast<const i4v *>(As + row * kStageBytes +
+                                               swz_chunk(row, h * 4 + g) * 16);
+      }
+#pragma unroll
+      for (int j = 0; j < FNW; ++j) {
+        const int row = wn0 + 16 * j + l16;
+        fb[j] = *reinterpret_cast<const i4v *>(Bs + row * kStageBytes +
+                                               swz_chunk(row, h * 4 + g) * 16);
+      }
+#pragma unroll
+      for (int i = 0; i < FMW; ++i)
+#pragma unroll
+        for (int j = 0; j < FNW; ++j) acc[i][j] = M::mma(fa[i], fb[j], acc[i][j]);
+    }
+    const bool seg_last = cur.st + 1 == seg_len(cur.seg, a);
+    if (M::CHUNK_STAGES > 0 && ((cur.st + 1) % (M::CHUNK_STAGES > 0 ? M::CHUNK_STAGES : 1) == 0 ||
+                                seg_last)) {
+#pragma unroll
+      for (int i = 0; i < FMW; ++i)
+#pragma unroll
+        for (int j = 0; j < FNW; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            dacc[i][j][r] += (int)acc[i][j][r];
+            acc[i][j][r] = 0;
+          }
+    }
+    if (t + 1 < T && seg_last && cur.p == pmax_of(cur.d, a.s))
+      fold_partials<M, FMW, FNW, S::THREADS>(acc, dacc, plane, ldexp(1.0, -a.bits * cur.d),
+                                             cur.seg == 0 && cur.d == 2);
+    advance(cur, a);
+  }
+
+  // Last diagonal of the last segment, then the epilogue.
+  const bool only = a.s == 1 && a.seg_stages >= a.total_stages;  // a single fold in all
+  finish_tile<M, FMW, FNW, S::THREADS>(a, acc, dacc, plane, only, m0 + wm0 + 4 * g,
+                                       n0 + wn0 + l16);
 }
 
 template <typename K>
@@ -411,6 +614,47 @@ int ensure_lds(K kern, size_t bytes) {
   MG_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   return MG_OK;
+}
+
+template <int ALGO, int WGM, int WGN, int FMW, int FNW>
+int launch_split_t(const SplitArgs &a, const SplitLayout &L, hipStream_t s) {
+  typedef SplitShape<WGM, WGN, FMW, FNW> S;
+  // Register budget: INT8 accumulators fit two 4-wavefront workgroups per CU
+  // for the 128x128 tiles; bigger tiles and BF16 run one per CU.
+  constexpr int MINB = (ALGO == MG_SPLIT_I8 && FMW * FNW <= 16) ? 2 : 1;
+  auto kern = split_gemm_kernel<ALGO, WGM, WGN, FMW, FNW, MINB>;
+  static int once = ensure_lds(kern, S::LDS_BYTES);
+  if (once != MG_OK) return once;
+  const int tiles_m = (int)(L.mp / S::BM), tiles_n = (int)(L.np / S::BN);
+  hipLaunchKernelGGL(kern, dim3(tiles_m * tiles_n), dim3(S::THREADS), S::LDS_BYTES, s, a, tiles_m,
+                     tiles_n);
+  MG_HIP_TRY(hipGetLastError());
+  return MG_OK;
+}
+
+template <int ALGO, int WGM, int WGN, int FMW, int FNW, int NS>
+int launch_split_dma_t(const SplitArgs &a, const SplitLayout &L, hipStream_t s) {
+  typedef SplitDmaShape<WGM, WGN, FMW, FNW, NS> S;
+  auto kern = split_gemm_dma_kernel<ALGO, WGM, WGN, FMW, FNW, NS>;
+  static int once = ensure_lds(kern, S::LDS_BYTES);
+  if (once != MG_OK) return once;
+  const int tiles_m = (int)(L.mp / S::BM), tiles_n = (int)(L.np / S::BN);
+  hipLaunchKernelGGL(kern, dim3(tiles_m * tiles_n), dim3(S::THREADS), S::LDS_BYTES, s, a, tiles_m,
+                     tiles_n);
+  MG_HIP_TRY(hipGetLastError());
+  return MG_OK;
+}
+
+template <int WGM, int WGN, int FMW, int FNW, int NS>
+int launch_split_dma(int algo, const SplitArgs &a, const SplitLayout &L, hipStream_t s) {
+  return algo == MG_SPLIT_BF16 ? launch_split_dma_t<MG_SPLIT_BF16, WGM, WGN, FMW, FNW, NS>(a, L, s)
+                               : launch_split_dma_t<MG_SPLIT_I8, WGM, WGN, FMW, FNW, NS>(a, L, s);
+}
+
+template <int WGM, int WGN, int FMW, int FNW>
+int launch_split(int algo, const SplitArgs &a, const SplitLayout &L, hipStream_t s) {
+  return algo == MG_SPLIT_BF16 ? launch_split_t<MG_SPLIT_BF16, WGM, WGN, FMW, FNW>(a, L, s)
+                               : launch_split_t<MG_SPLIT_I8, WGM, WGN, FMW, FNW>(a, L, s);
 }
 
 }  // namespace
@@ -432,9 +676,9 @@ int split_layout(int algo, int slices, int64_t m, int64_t n, int64_t k, SplitLay
     set_error("negative extent");
     return MG_ERR_INVALID_ARG;
   }
-  L->mp = round_up(std::max<int64_t>(m, 1), kSplitTile);
-  L->np = round_up(std::max<int64_t>(n, 1), kSplitTile);
-  L->kp = round_up(std::max<int64_t>(k, 1), kSplitTile);
+  L->mp = round_up(std::max<int64_t>(m, 1), kSplitTileMN);
+  L->np = round_up(std::max<int64_t>(n, 1), kSplitTileMN);
+  L->kp = round_up(std::max<int64_t>(k, 1), kSplitTileK);
   L->elem_bytes = algo == MG_SPLIT_BF16 ? 2 : 1;
   int64_t off = 0;
   L->e_off = off;
@@ -498,8 +742,19 @@ int split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, const d
   return MG_OK;
 }
 
+int split_num_cfgs() { return 6; }
+
+// Product-kernel work division (measured on MI355X at n = 4096): the 256x256
+// direct-to-LDS tile once every CU gets one, then the 128x256 one, else the
+// register-staged 128x128 tile.
+int split_pick_cfg(int64_t mp, int64_t np) {
+  if ((mp / 256) * (np / 256) >= 256) return 4;
+  if ((mp / 128) * (np / 256) >= 256) return 2;
+  return 0;
+}
+
 int split_multiply(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
-                   double beta, double *C, int64_t ldc, void *ws, hipStream_t s) {
+                   double beta, double *C, int64_t ldc, void *ws, hipStream_t s, int cfg) {
   SplitLayout L;
   int rc = split_layout(algo, slices, m, n, k, &L);
   if (rc != MG_OK) return rc;
@@ -534,26 +789,22 @@ int split_multiply(int algo, int slices, int64_t m, int64_t n, int64_t k, double
   a.seg_stages = (int)std::min<int64_t>(seg_stages, a.total_stages);
   a.alpha = alpha;
   a.beta = beta;
-  const int tiles_m = (int)(L.mp / kSBM), tiles_n = (int)(L.np / kSBN);
-  const size_t lds = 2 * (size_t)(kSBM + kSBN) * kPitch;
-  if (algo == MG_SPLIT_BF16) {
-    static int once = ensure_lds(split_gemm_kernel<MG_SPLIT_BF16>, lds);
-    if (once != MG_OK) return once;
-    hipLaunchKernelGGL(split_gemm_kernel<MG_SPLIT_BF16>, dim3(tiles_m * tiles_n), dim3(256), lds, s,
-                       a, tiles_m, tiles_n);
-  } else {
-    static int once = ensure_lds(split_gemm_kernel<MG_SPLIT_I8>, lds);
-    if (once != MG_OK) return once;
-    hipLaunchKernelGGL(split_gemm_kernel<MG_SPLIT_I8>, dim3(tiles_m * tiles_n), dim3(256), lds, s,
-                       a, tiles_m, tiles_n);
+  if (cfg < 0) cfg = split_pick_cfg(L.mp, L.np);
+  switch (cfg) {
+    case 0: return launch_split<2, 2, 4, 4>(algo, a, L, s);          // 128x128, 4 waves, registers
+    case 1: return launch_split_dma<2, 2, 4, 4, 4>(algo, a, L, s);   // 128x128, 4 waves, ring of 4
+    case 2: return launch_split_dma<2, 4, 4, 4, 3>(algo, a, L, s);   // 128x256, 8 waves, ring of 3
+    case 3: return launch_split_dma<2, 2, 8, 4, 3>(algo, a, L, s);   // 256x128, 4 waves, ring of 3
+    case 4: return launch_split_dma<4, 4, 4, 4, 2>(algo, a, L, s);   // 256x256, 16 waves, ring of 2
+    case 5: return launch_split_dma<2, 4, 4, 4, 2>(algo, a, L, s);   // 128x256, 8 waves, ring of 2
   }
-  MG_HIP_TRY(hipGetLastError());
-  return MG_OK;
+  set_error("unknown split cfg %d", cfg);
+  return MG_ERR_INVALID_ARG;
 }
 
 int gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
                const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
-               double *C, int64_t ldc, void *ws, int64_t ws_bytes, hipStream_t s) {
+               double *C, int64_t ldc, void *ws, int64_t ws_bytes, hipStream_t s, int cfg) {
   if (m == 0 || n == 0) return MG_OK;
   SplitLayout L;
   int rc = split_layout(algo, slices, m, n, k, &L);
@@ -566,7 +817,7 @@ int gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double alp
   }
   rc = split_prepare(algo, slices, m, n, k, A, lda, B, ldb, ws, s);
   if (rc != MG_OK) return rc;
-  return split_multiply(algo, slices, m, n, k, alpha, beta, C, ldc, ws, s);
+  return split_multiply(algo, slices, m, n, k, alpha, beta, C, ldc, ws, s, cfg);
 }
 
 int gemm_split_pooled(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,

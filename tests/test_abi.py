@@ -47,7 +47,8 @@ def test_version_and_cfgs():
         assert mg.tile_cfg_info(c, mg.F32)["bk"] == 2 * info["bk"]
     with pytest.raises(mg.MgError):
         mg.tile_cfg_info(99)
-    assert mg.pick_tile_cfg(8192, 8192, 8192) == 2
+    assert mg.pick_tile_cfg(8192, 8192, 8192) == 5
+    assert mg.pick_tile_cfg(2048, 2048, 2048) == 8
     assert 0 <= mg.pick_tile_cfg(16, 16, 16) < mg.num_tile_cfgs()
 
 
@@ -94,14 +95,15 @@ def test_alpha_zero_allows_null_ab():
 
 
 def test_split_layout_and_errors():
-    L = mg.split_layout(mg.SPLIT_I8, 7, 100, 200, 300)
-    assert (L["mp"], L["np"], L["kp"], L["elem_bytes"]) == (128, 256, 384, 1)
+    L = mg.split_layout(mg.SPLIT_I8, 7, 100, 300, 300)
+    assert (L["mp"], L["np"], L["kp"], L["elem_bytes"]) == (256, 512, 384, 1)
     assert L["a_off"] % 256 == 0 and L["b_off"] % 256 == 0
-    assert L["b_off"] >= L["a_off"] + 7 * 128 * 384
-    assert L["p_off"] >= L["b_off"] + 7 * 256 * 384
-    assert L["total_bytes"] >= L["p_off"] + 8 * 128 * 256
+    assert L["b_off"] >= L["a_off"] + 7 * 256 * 384
+    assert L["p_off"] >= L["b_off"] + 7 * 512 * 384
+    assert L["total_bytes"] >= L["p_off"] + 8 * 256 * 512
     Lb = mg.split_layout(mg.SPLIT_BF16, 6, 1, 1, 1)
-    assert (Lb["mp"], Lb["np"], Lb["kp"], Lb["elem_bytes"]) == (128, 128, 128, 2)
+    assert (Lb["mp"], Lb["np"], Lb["kp"], Lb["elem_bytes"]) == (256, 256, 128, 2)
+    assert mg.split_num_cfgs() == 6
     assert mg.split_default_slices(mg.SPLIT_I8) == 7
     assert mg.split_default_slices(mg.SPLIT_BF16) == 6
     with pytest.raises(mg.MgError):

@@ -225,3 +225,17 @@ def test_workspace_below_operands_is_not_an_overlap():
     mg.gemm_split(dA, dB, dC, 1.0, 1.0, algo=algo, slices=s, workspace=ws)
     torch.cuda.synchronize()
     assert np.array_equal(dC.cpu().numpy(), osplit.split_gemm(1.0, A, B, 1.0, C, s, "i8"))
+
+
+@pytest.mark.parametrize("kind", ["i8", "bf16"])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5])
+def test_split_work_divisions_bit_exact(kind, cfg):
+    """Every work division of the product kernel gives the oracle's bits."""
+    algo = ALGOS[kind]
+    s = mg.split_default_slices(algo)
+    m, n, k = 300, 520, 384
+    A, B, C = spread(75 + cfg, m, n, k)
+    dC = to_dev(C)
+    mg.gemm_split(to_dev(A), to_dev(B), dC, 1.5, -0.5, algo=algo, slices=s, cfg=cfg)
+    torch.cuda.synchronize()
+    assert np.array_equal(dC.cpu().numpy(), osplit.split_gemm(1.5, A, B, -0.5, C, s, kind))

@@ -150,7 +150,9 @@ int mg_gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double 
  * 0: 128x128 tile on 4 wavefronts, register-staged double buffer;
  * with a ring of direct-to-LDS stages: 1: 128x128 on 4 (ring of 4),
  * 2: 128x256 on 8 (ring of 3), 3: 256x128 on 4 (ring of 3), 4: 256x256 on
- * 16 (ring of 2), 5: 128x256 on 8 (ring of 2).  mg_gemm_split picks by size;
+ * 16 (ring of 2), 5: 128x256 on 8 (ring of 2); with 64-byte k stages:
+ * 6: 256x256 on 8 (ring of 4), 7: 256x256 on 16 (ring of 4), 8: 128x256 on 8
+ * (ring of 6).  mg_gemm_split picks by size;
  * mg_gemm_split_cfg takes cfg explicitly (-1 = pick).  MG_ERR_INVALID_ARG for
  * an unknown cfg. */
 int mg_split_num_cfgs(void);
@@ -163,12 +165,13 @@ int mg_gemm_split_cfg(int algo, int slices, int cfg, int64_t m, int64_t n, int64
  * Many independent problems C_i <- alpha_i A_i B_i + beta_i C_i (each the
  * Section 4.2 operation) in ONE persistent launch.  A plan validates the
  * problems, picks a tile class per problem (from a tuning table or a
- * heuristic), builds a device work list of macro-tiles sorted longest first,
- * and on first launch captures [counter reset, persistent kernel] in a HIP
- * graph that later launches replay.  The grid is (CUs x occupancy)
- * workgroups; each pulls tiles through an atomic counter (blocks are
- * otherwise independent, Section 3.2), so a problem's result is the same
- * whatever else is in the batch.
+ * heuristic), builds a device work list of macro-tiles sorted longest first
+ * (each record carries its problem's arguments), and on first launch
+ * captures the persistent kernel in a HIP graph that later launches replay.
+ * The grid is (CUs x occupancy) workgroups; workgroup b computes tiles b,
+ * b+G, b+2G, ... of the list (blocks are independent and never synchronise,
+ * Section 3.2), so a problem's result is the same whatever else is in the
+ * batch.
  * Problems may share A and B; no C may overlap another problem's C, A or B
  * (checked on the byte spans [first element, last element], so interleaved
  * sub-blocks of one buffer are rejected).  dtype MG_F64 or MG_F32. */

@@ -20,12 +20,11 @@ int64_t tune_bucket_rep(int b);
 int grouped_class_tile(int cls, int *bm, int *bn);
 int heuristic_class(int64_t m, int64_t n);
 
-// Host work list of a batch: problem descriptors (device layout) and tiles
-// sorted longest first, ready to be copied to the device as raw bytes.
+// Host work list of a batch: tile records (device layout, problem arguments
+// inline) sorted longest first, ready to be copied to the device as bytes.
 struct WorkList {
   int dtype = MG_F64;
   int ntiles = 0;
-  std::vector<unsigned char> probs;
   std::vector<unsigned char> tiles;
   mg_plan_stats stats{};
 };
@@ -34,10 +33,8 @@ int build_worklist(int dtype, int64_t count, const mg_problem *probs, const mg_t
                    WorkList *out);
 // Persistent grid (CUs x occupancy, at most ntiles) for the grouped kernel.
 int grouped_grid(int dtype, int ntiles, int *grid, int *occupancy);
-// Enqueues counter reset + persistent kernel over device copies of a work list.
-int launch_worklist(int dtype, const void *d_probs, const void *d_tiles, int ntiles,
-                    int *d_counter, int grid, hipStream_t s);
-size_t tile_desc_bytes();
+// Enqueues the persistent kernel over a device copy of a work list.
+int launch_worklist(int dtype, const void *d_tiles, int ntiles, int grid, hipStream_t s);
 
 int plan_create(int dtype, int64_t count, const mg_problem *probs, const mg_tune_table *table,
                 Plan **out);

@@ -1,18 +1,18 @@
 // Batched uneven GEMMs in one persistent launch.
 //
 // A plan turns a list of independent problems C_i <- alpha_i A_i B_i +
-// beta_i C_i into a device work list of macro-tiles (each tagged with its
-// problem and a tile class from the tuning table), sorted longest first.  One
-// persistent kernel of (CUs x occupancy) workgroups pulls tiles from the list
-// through an atomic counter and runs the same per-tile code as the single-
-// problem kernel, so a problem's result does not depend on what else is in
-// the batch.  The launch (counter reset + persistent kernel) is captured once
-// in a HIP graph and replayed.
+// beta_i C_i into a device work list of macro-tiles (each record carries its
+// problem's arguments, tile coordinates and a tile class from the tuning
+// table), sorted longest first.  One persistent kernel of (CUs x occupancy)
+// workgroups walks the list round-robin (workgroup b takes tiles b, b+G,
+// b+2G, ...: with the list in decreasing cost this deals the expensive tiles
+// out evenly) and runs the same per-tile code as the single-problem kernel,
+// so a problem's result does not depend on what else is in the batch.  Each
+// workgroup loads its next record while it computes the current tile.  The
+// launch is captured once in a HIP graph and replayed.
 //
-// In the paper's terms (Section 3.2): blocks are independent and are not
-// synchronised with each other; the only shared state is the work counter,
-// updated with an atomic (the paper's footnote on atomics serialising access
-// to global memory).
+// In the paper's terms (Section 3.2): blocks are independent and are never
+// synchronised with each other; they share nothing but the read-only list.
 #include "grouped.h"
 
 #include <algorithm>
@@ -34,15 +34,13 @@ constexpr int kClsBN[kNumGroupedClasses] = {64, 32, 32};
 constexpr int kScaleCls = 15;  // C <- beta*C only (alpha == 0 or k == 0)
 constexpr int kScaleTile = 64;
 
+// One macro-tile of work: the problem's arguments inline (one load per tile).
 template <typename T>
-struct GProb {
+struct GTileRec {
   GemmArgs<T> g;
-};
-
-struct GTile {
-  int prob;
   int tm, tn;
   int cls;  // class | (vec_ok << 4)
+  int pad;
 };
 
 template <typename T>
@@ -56,50 +54,48 @@ __device__ __forceinline__ void scale_tile(const GemmArgs<T> &g, int m0, int n0)
   }
 }
 
-// Persistent loop.  Thread 0 fetches the next tile index while the
-// workgroup computes the current one, so the atomic's latency is hidden; the
-// barriers inside gemm_tile order its write before the read after the tile.
 template <typename T>
-__global__ __launch_bounds__(kTileThreads, 3) void grouped_kernel(const GProb<T> *__restrict__ probs,
-                                                                  const GTile *__restrict__ tiles,
-                                                                  int ntiles, int *counter) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  __shared__ int s_next;
-  T *smem = reinterpret_cast<T *>(lds_raw);
-  if (threadIdx.x == 0) s_next = atomicAdd(counter, 1);
-  __syncthreads();
-  int w = s_next;
-  __syncthreads();
-  while (w < ntiles) {
-    if (threadIdx.x == 0) s_next = atomicAdd(counter, 1);
-    const GTile t = tiles[w];
-    const GemmArgs<T> g = probs[t.prob].g;
-    const bool vec = (t.cls >> 4) & 1;
-    switch (t.cls & 15) {
-      case 0:
-        if (vec) gemm_tile<T, 64, 64, true>(g, t.tm * 64, t.tn * 64, smem);
-        else gemm_tile<T, 64, 64, false>(g, t.tm * 64, t.tn * 64, smem);
-        break;
-      case 1:
-        if (vec) gemm_tile<T, 64, 32, true>(g, t.tm * 64, t.tn * 32, smem);
-        else gemm_tile<T, 64, 32, false>(g, t.tm * 64, t.tn * 32, smem);
-        break;
-      case 2:
-        if (vec) gemm_tile<T, 32, 32, true>(g, t.tm * 32, t.tn * 32, smem);
-        else gemm_tile<T, 32, 32, false>(g, t.tm * 32, t.tn * 32, smem);
-        break;
-      default:
-        scale_tile<T>(g, t.tm * kScaleTile, t.tn * kScaleTile);
-        break;
-    }
-    __syncthreads();
-    w = s_next;
-    __syncthreads();
+__device__ __forceinline__ void run_tile(const GTileRec<T> &t, T *smem) {
+  const bool vec = (t.cls >> 4) & 1;
+  switch (t.cls & 15) {
+    case 0:
+      if (vec) gemm_tile<T, 64, 64, true>(t.g, t.tm * 64, t.tn * 64, smem);
+      else gemm_tile<T, 64, 64, false>(t.g, t.tm * 64, t.tn * 64, smem);
+      break;
+    case 1:
+      if (vec) gemm_tile<T, 64, 32, true>(t.g, t.tm * 64, t.tn * 32, smem);
+      else gemm_tile<T, 64, 32, false>(t.g, t.tm * 64, t.tn * 32, smem);
+      break;
+    case 2:
+      if (vec) gemm_tile<T, 32, 32, true>(t.g, t.tm * 32, t.tn * 32, smem);
+      else gemm_tile<T, 32, 32, false>(t.g, t.tm * 32, t.tn * 32, smem);
+      break;
+    default:
+      scale_tile<T>(t.g, t.tm * kScaleTile, t.tn * kScaleTile);
+      break;
   }
 }
 
-__global__ void reset_counter_kernel(int *counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+// Persistent loop over tiles blockIdx.x, +gridDim.x, ...; the next record is
+// loaded (uniform, scalar loads) before the current tile is computed.
+template <typename T>
+__global__ __launch_bounds__(kTileThreads, 3) void grouped_kernel(
+    const GTileRec<T> *__restrict__ tiles, int ntiles) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T *smem = reinterpret_cast<T *>(lds_raw);
+  int w = blockIdx.x;
+  if (w >= ntiles) return;
+  GTileRec<T> cur = tiles[w];
+  for (;;) {
+    const int nw = w + (int)gridDim.x;
+    GTileRec<T> nxt = cur;
+    if (nw < ntiles) nxt = tiles[nw];
+    run_tile<T>(cur, smem);
+    if (nw >= ntiles) break;
+    __syncthreads();  // LDS of this tile fully consumed before the next one
+    w = nw;
+    cur = nxt;
+  }
 }
 
 template <typename T>
@@ -150,9 +146,7 @@ struct Plan {
   int64_t count = 0;
   int ntiles = 0;
   int grid = 0;
-  void *d_probs = nullptr;
   void *d_tiles = nullptr;
-  int *d_counter = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   mg_plan_stats stats{};
@@ -162,14 +156,14 @@ namespace {
 
 template <typename T>
 int build_t(int64_t count, const mg_problem *probs, const mg_tune_table *table, WorkList *out) {
-  std::vector<GProb<T>> hp((size_t)count);
-  std::vector<GTile> tiles;
+  std::vector<GemmArgs<T>> hp((size_t)count);
+  std::vector<GTileRec<T>> tiles;
   std::vector<double> cost;
   double flops = 0, bytes = 0;
   int64_t per_cls[kNumGroupedClasses + 1] = {0};
   for (int64_t i = 0; i < count; ++i) {
     const mg_problem &q = probs[i];
-    GemmArgs<T> &g = hp[(size_t)i].g;
+    GemmArgs<T> &g = hp[(size_t)i];
     g.A = static_cast<const T *>(q.A);
     g.B = static_cast<const T *>(q.B);
     g.C = static_cast<T *>(q.C);
@@ -186,7 +180,7 @@ int build_t(int64_t count, const mg_problem *probs, const mg_tune_table *table, 
       const int tm = (int)ceil_div(q.m, kScaleTile), tn = (int)ceil_div(q.n, kScaleTile);
       for (int a = 0; a < tm; ++a)
         for (int b = 0; b < tn; ++b) {
-          tiles.push_back(GTile{(int)i, a, b, kScaleCls});
+          tiles.push_back(GTileRec<T>{g, a, b, kScaleCls, 0});
           cost.push_back((double)kScaleTile * kScaleTile);
         }
       per_cls[kNumGroupedClasses] += (int64_t)tm * tn;
@@ -203,7 +197,7 @@ int build_t(int64_t count, const mg_problem *probs, const mg_tune_table *table, 
     const int tm = (int)ceil_div(q.m, bm), tn = (int)ceil_div(q.n, bn);
     for (int a = 0; a < tm; ++a)
       for (int b = 0; b < tn; ++b) {
-        tiles.push_back(GTile{(int)i, a, b, cls | (vec ? 16 : 0)});
+        tiles.push_back(GTileRec<T>{g, a, b, cls | (vec ? 16 : 0), 0});
         // MFMA work of the padded tile plus its operand traffic (in FLOP-equivalents)
         cost.push_back(2.0 * bm * bn * (double)round_up(q.k, Mfma<T>::BK) +
                        16.0 * (bm + bn) * (double)q.k);
@@ -217,17 +211,14 @@ int build_t(int64_t count, const mg_problem *probs, const mg_tune_table *table, 
     set_error("too many tiles");
     return MG_ERR_INVALID_ARG;
   }
-  // Longest-processing-time order: the atomic counter then hands the biggest
-  // remaining tile to whichever workgroup frees up first (greedy list
-  // scheduling, within 4/3 of the optimal makespan).
+  // Longest-processing-time order: dealt round-robin to the workgroups, the
+  // expensive tiles spread evenly and the cheap ones fill in at the end.
   std::vector<int> order(tiles.size());
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
   out->dtype = std::is_same<T, double>::value ? MG_F64 : MG_F32;
-  out->probs.resize(hp.size() * sizeof(GProb<T>));
-  if (!hp.empty()) std::memcpy(out->probs.data(), hp.data(), out->probs.size());
-  out->tiles.resize(tiles.size() * sizeof(GTile));
-  GTile *dst = reinterpret_cast<GTile *>(out->tiles.data());
+  out->tiles.resize(tiles.size() * sizeof(GTileRec<T>));
+  GTileRec<T> *dst = reinterpret_cast<GTileRec<T> *>(out->tiles.data());
   for (size_t i = 0; i < order.size(); ++i) dst[i] = tiles[(size_t)order[i]];
   out->ntiles = (int)tiles.size();
   mg_plan_stats &st = out->stats;
@@ -262,18 +253,15 @@ int occupancy_t(int *cus, int *occ) {
 }
 
 template <typename T>
-int launch_t(const void *d_probs, const void *d_tiles, int ntiles, int *d_counter, int grid,
-             hipStream_t s) {
-  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, d_counter);
+int launch_t(const void *d_tiles, int ntiles, int grid, hipStream_t s) {
   hipLaunchKernelGGL(grouped_kernel<T>, dim3(grid), dim3(kTileThreads), grouped_lds_bytes<T>(), s,
-                     static_cast<const GProb<T> *>(d_probs), static_cast<const GTile *>(d_tiles),
-                     ntiles, d_counter);
+                     static_cast<const GTileRec<T> *>(d_tiles), ntiles);
   MG_HIP_TRY(hipGetLastError());
   return MG_OK;
 }
 
 int launch_raw(Plan *p, hipStream_t s) {
-  return launch_worklist(p->dtype, p->d_probs, p->d_tiles, p->ntiles, p->d_counter, p->grid, s);
+  return launch_worklist(p->dtype, p->d_tiles, p->ntiles, p->grid, s);
 }
 
 }  // namespace
@@ -293,14 +281,11 @@ int grouped_grid(int dtype, int ntiles, int *grid, int *occupancy) {
   return MG_OK;
 }
 
-int launch_worklist(int dtype, const void *d_probs, const void *d_tiles, int ntiles,
-                    int *d_counter, int grid, hipStream_t s) {
+int launch_worklist(int dtype, const void *d_tiles, int ntiles, int grid, hipStream_t s) {
   if (ntiles == 0) return MG_OK;
-  return dtype == MG_F64 ? launch_t<double>(d_probs, d_tiles, ntiles, d_counter, grid, s)
-                         : launch_t<float>(d_probs, d_tiles, ntiles, d_counter, grid, s);
+  return dtype == MG_F64 ? launch_t<double>(d_tiles, ntiles, grid, s)
+                         : launch_t<float>(d_tiles, ntiles, grid, s);
 }
-
-size_t tile_desc_bytes() { return sizeof(GTile); }
 
 int plan_create(int dtype, int64_t count, const mg_problem *probs, const mg_tune_table *table,
                 Plan **out) {
@@ -322,12 +307,7 @@ int plan_create(int dtype, int64_t count, const mg_problem *probs, const mg_tune
     if (!src.empty()) MG_HIP_TRY(hipMemcpy(*dst, src.data(), src.size(), hipMemcpyHostToDevice));
     return MG_OK;
   };
-  if (rc == MG_OK) rc = upload(&p->d_probs, wl.probs);
   if (rc == MG_OK) rc = upload(&p->d_tiles, wl.tiles);
-  if (rc == MG_OK && hipMalloc(&p->d_counter, 256) != hipSuccess) {
-    set_error("hipMalloc failed for the work counter");
-    rc = MG_ERR_HIP;
-  }
   if (rc != MG_OK) {
     plan_destroy(p);
     return rc;
@@ -373,9 +353,7 @@ void plan_destroy(Plan *p) {
   if (p == nullptr) return;
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
-  if (p->d_probs) (void)hipFree(p->d_probs);
   if (p->d_tiles) (void)hipFree(p->d_tiles);
-  if (p->d_counter) (void)hipFree(p->d_counter);
   delete p;
 }
 

@@ -44,7 +44,6 @@ struct Lane {
   size_t d_cap = 0;
   void *h_buf = nullptr;  // pinned staging
   size_t h_cap = 0;
-  int *d_counter = nullptr;  // two counters, 256 bytes apart
   std::vector<Req *> batch;
   int64_t sim_done_ns = 0;  // host simulation: when the batch "completes"
   bool busy = false;      // owns a batch (being launched or in flight)
@@ -140,10 +139,8 @@ void launch_batch(Server *S, Lane &L, int64_t batch_id) {
   WorkList w64, w32;
   int rc = build_worklist(MG_F64, (int64_t)p64.size(), p64.data(), tab, &w64);
   if (rc == MG_OK) rc = build_worklist(MG_F32, (int64_t)p32.size(), p32.data(), tab, &w32);
-  const size_t o_p64 = 0;
-  const size_t o_t64 = align256(o_p64 + w64.probs.size());
-  const size_t o_p32 = align256(o_t64 + w64.tiles.size());
-  const size_t o_t32 = align256(o_p32 + w32.probs.size());
+  const size_t o_t64 = 0;
+  const size_t o_t32 = align256(o_t64 + w64.tiles.size());
   const size_t total = align256(o_t32 + w32.tiles.size());
   if (rc == MG_OK && total > 0) rc = ensure_capacity(L, total);
   if (rc == MG_OK && total > 0) {
@@ -151,18 +148,16 @@ void launch_batch(Server *S, Lane &L, int64_t batch_id) {
     auto put = [&](size_t off, const std::vector<unsigned char> &v) {
       if (!v.empty()) std::memcpy(h + off, v.data(), v.size());
     };
-    put(o_p64, w64.probs);
     put(o_t64, w64.tiles);
-    put(o_p32, w32.probs);
     put(o_t32, w32.tiles);
     if (hipMemcpyAsync(L.d_buf, L.h_buf, total, hipMemcpyHostToDevice, L.s) != hipSuccess)
       rc = MG_ERR_HIP;
     unsigned char *d = static_cast<unsigned char *>(L.d_buf);
     int grid = 1;
     if (rc == MG_OK && w64.ntiles > 0 && (rc = grouped_grid(MG_F64, w64.ntiles, &grid, nullptr)) == MG_OK)
-      rc = launch_worklist(MG_F64, d + o_p64, d + o_t64, w64.ntiles, L.d_counter, grid, L.s);
+      rc = launch_worklist(MG_F64, d + o_t64, w64.ntiles, grid, L.s);
     if (rc == MG_OK && w32.ntiles > 0 && (rc = grouped_grid(MG_F32, w32.ntiles, &grid, nullptr)) == MG_OK)
-      rc = launch_worklist(MG_F32, d + o_p32, d + o_t32, w32.ntiles, L.d_counter + 64, grid, L.s);
+      rc = launch_worklist(MG_F32, d + o_t32, w32.ntiles, grid, L.s);
   }
   for (Req *q : L.batch)
     if (q->r.algo == MG_NATIVE && rc != MG_OK) q->res.status = rc;
@@ -262,7 +257,6 @@ void destroy_lanes(Server *S) {
     if (L.s) (void)hipStreamDestroy(L.s);
     if (L.d_buf) (void)hipFree(L.d_buf);
     if (L.h_buf) (void)hipHostFree(L.h_buf);
-    if (L.d_counter) (void)hipFree(L.d_counter);
   }
 }
 
@@ -297,7 +291,7 @@ int server_create(const mg_server_opts *o, Server **out) {
   for (Lane &L : S->lanes) {
     if (hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&L.ev, hipEventDisableTiming) != hipSuccess ||
-        hipMalloc(&L.d_counter, 512) != hipSuccess || ensure_capacity(L, (size_t)1 << 20) != MG_OK) {
+        ensure_capacity(L, (size_t)1 << 20) != MG_OK) {
       destroy_lanes(S);
       delete S;
       set_error("server resource creation failed");

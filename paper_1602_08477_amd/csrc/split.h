@@ -33,7 +33,7 @@ int split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, const d
 
 // Work divisions of the product kernel; cfg < 0 picks by size.
 int split_num_cfgs();
-int split_pick_cfg(int64_t mp, int64_t np);
+int split_pick_cfg(int algo, int64_t mp, int64_t np);
 
 // Slice products + recombination + epilogue from a prepared workspace.
 int split_multiply(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,

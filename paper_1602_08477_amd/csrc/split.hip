@@ -452,24 +452,31 @@ __global__ __launch_bounds__((SplitShape<WGM, WGN, FMW, FNW>::THREADS), MINB) vo
 // Variant with direct global->LDS loads (gfx950 global_load_lds_dwordx4) into
 // an NS-stage ring, so NS-1 stages of slice data are in flight while the
 // matrix cores work on the current one, without staging registers.
-// LDS rows are 128 bytes without padding; the 16-byte chunk c of row r is
-// stored at chunk c ^ ((r >> 1) & 7), which keeps both the DMA writes
-// (1 KB contiguous per wave instruction) and the fragment reads (16 rows,
-// one chunk each) free of bank conflicts.
-template <int WGM, int WGN, int FMW, int FNW, int NS>
+// LDS rows are SB (64 or 128) bytes without padding.  The 16-byte chunk c of
+// row r is stored at chunk c ^ swz(r), swz(r) = (r >> 1) & 7 for 128-byte rows
+// and (r >> 2) & 3 for 64-byte rows: 16 consecutive rows then cover every
+// bank once, so both the DMA writes (1 KB contiguous per wave instruction)
+// and the fragment reads (16 rows, one chunk each) are free of bank conflicts.
+template <int WGM, int WGN, int FMW, int FNW, int NS, int SB>
 struct SplitDmaShape {
   static constexpr int THREADS = 64 * WGM * WGN;
   static constexpr int WAVES = WGM * WGN;
   static constexpr int BM = WGM * 16 * FMW, BN = WGN * 16 * FNW;
-  static constexpr int STAGE = (BM + BN) * kStageBytes;  // bytes
+  static constexpr int STAGE = (BM + BN) * SB;  // bytes
   static constexpr size_t LDS_BYTES = (size_t)NS * STAGE;
-  static constexpr int IA = BM / 8 / WAVES;  // DMA instructions (8 rows each) per wave, A
-  static constexpr int IB = BN / 8 / WAVES;
-  static_assert(IA * 8 * WAVES == BM && IB * 8 * WAVES == BN, "whole DMA rows per wave");
+  static constexpr int CPR = SB / 16;         // chunks per row
+  static constexpr int RPI = 64 / CPR;        // rows per DMA instruction (1 KB)
+  static constexpr int IA = BM / RPI / WAVES;  // DMA instructions per wave, A
+  static constexpr int IB = BN / RPI / WAVES;
+  static_assert(SB == 64 || SB == 128, "stage depth");
+  static_assert(IA * RPI * WAVES == BM && IB * RPI * WAVES == BN, "whole DMA rows per wave");
   static_assert(NS >= 2, "at least double buffering");
 };
 
-__device__ __forceinline__ int swz_chunk(int row, int chunk) { return chunk ^ ((row >> 1) & 7); }
+template <int SB>
+__device__ __forceinline__ int swz_chunk(int row, int chunk) {
+  return SB == 128 ? chunk ^ ((row >> 1) & 7) : chunk ^ ((row >> 2) & 3);
+}
 
 template <int N>
 __device__ __forceinline__ void wait_vmcnt() {
@@ -484,12 +491,15 @@ __device__ __forceinline__ void dma16(const unsigned char *src, unsigned char *l
                                    0);
 }
 
-template <int ALGO, int WGM, int WGN, int FMW, int FNW, int NS>
-__global__ __launch_bounds__((SplitDmaShape<WGM, WGN, FMW, FNW, NS>::THREADS), 1) void
+// `a.seg_stages` and `a.total_stages` count SB-byte stages here.
+template <int ALGO, int WGM, int WGN, int FMW, int FNW, int NS, int SB>
+__global__ __launch_bounds__((SplitDmaShape<WGM, WGN, FMW, FNW, NS, SB>::THREADS), 1) void
 split_gemm_dma_kernel(SplitArgs a, int tiles_m, int tiles_n) {
   typedef SplitMma<ALGO> M;
   typedef typename M::acc_t Acc;
-  typedef SplitDmaShape<WGM, WGN, FMW, FNW, NS> S;
+  typedef SplitDmaShape<WGM, WGN, FMW, FNW, NS, SB> S;
+  // FP32 chunk of 256 k for BF16 (512 bytes), in stages
+  constexpr int CHUNK = M::CHUNK_STAGES > 0 ? 512 / SB : 0;
   constexpr int BM = S::BM, BN = S::BN, STAGE = S::STAGE;
   constexpr int DPS = S::IA + S::IB;  // DMA instructions per step per wave
   extern __shared__ __align__(16) unsigned char lds[];
@@ -502,33 +512,32 @@ split_gemm_dma_kernel(SplitArgs a, int tiles_m, int tiles_n) {
   const int g = lane >> 4, l16 = lane & 15;
 
   const int64_t a_slice = (int64_t)a.mp * a.kp_bytes, b_slice = (int64_t)a.np * a.kp_bytes;
-  // DMA source offsets of this lane: instruction u covers rows 8*(wave*I + u) .. +7;
-  // the lane supplies row +lane/8, physical chunk lane%8 = logical swz_chunk(row, lane%8).
+  // DMA source offsets of this lane: instruction u covers RPI rows starting at
+  // RPI*(wave*I + u); the lane supplies row +lane/CPR, physical chunk lane%CPR,
+  // which holds logical chunk swz_chunk(row, lane%CPR).
   int64_t asrc[S::IA], bsrc[S::IB];
 #pragma unroll
   for (int u = 0; u < S::IA; ++u) {
-    const int row = 8 * (wave * S::IA + u) + (lane >> 3);
-    asrc[u] = (int64_t)(m0 + row) * a.kp_bytes + swz_chunk(row, lane & 7) * 16;
+    const int row = S::RPI * (wave * S::IA + u) + lane / S::CPR;
+    asrc[u] = (int64_t)(m0 + row) * a.kp_bytes + swz_chunk<SB>(row, lane % S::CPR) * 16;
   }
 #pragma unroll
   for (int u = 0; u < S::IB; ++u) {
-    const int row = 8 * (wave * S::IB + u) + (lane >> 3);
-    bsrc[u] = (int64_t)(n0 + row) * a.kp_bytes + swz_chunk(row, lane & 7) * 16;
+    const int row = S::RPI * (wave * S::IB + u) + lane / S::CPR;
+    bsrc[u] = (int64_t)(n0 + row) * a.kp_bytes + swz_chunk<SB>(row, lane % S::CPR) * 16;
   }
   double *plane = a.P + (int64_t)blockIdx.x * (BM * BN) + tid;  // this lane's partial sums
 
   auto issue = [&](const Step &x, int stage) {
-    const int64_t koff = (int64_t)(x.seg * a.seg_stages + x.st) * kStageBytes;
+    const int64_t koff = (int64_t)(x.seg * a.seg_stages + x.st) * SB;
     const unsigned char *pa = a.As + (x.p - 1) * a_slice + koff;
     const unsigned char *pb = a.Bs + (x.d - x.p - 1) * b_slice + koff;
     unsigned char *la = lds + stage * STAGE;
-    unsigned char *lb = la + BM * kStageBytes;
+    unsigned char *lb = la + BM * SB;
 #pragma unroll
-    for (int u = 0; u < S::IA; ++u)
-      dma16(pa + asrc[u], la + (wave * S::IA + u) * 8 * kStageBytes);
+    for (int u = 0; u < S::IA; ++u) dma16(pa + asrc[u], la + (wave * S::IA + u) * 1024);
 #pragma unroll
-    for (int u = 0; u < S::IB; ++u)
-      dma16(pb + bsrc[u], lb + (wave * S::IB + u) * 8 * kStageBytes);
+    for (int u = 0; u < S::IB; ++u) dma16(pb + bsrc[u], lb + (wave * S::IB + u) * 1024);
   };
 
   Acc acc[FMW][FNW];
@@ -563,21 +572,19 @@ split_gemm_dma_kernel(SplitArgs a, int tiles_m, int tiles_n) {
       advance(ld, a);
     }
     const unsigned char *As = lds + (t % NS) * STAGE;
-    const unsigned char *Bs = As + BM * kStageBytes;
+    const unsigned char *Bs = As + BM * SB;
 #pragma unroll
-    for (int h = 0; h < kStageBytes / 64; ++h) {
+    for (int h = 0; h < SB / 64; ++h) {
       i4v fa[FMW], fb[FNW];
 #pragma unroll
       for (int i = 0; i < FMW; ++i) {
         const int row = wm0 + 16 * i + l16;
-        fa[i] = *reinterpret_cast<const i4v *>(As + row * kStageBytes +
-                                               swz_chunk(row, h * 4 + g) * 16);
+        fa[i] = *reinterpret_cast<const i4v *>(As + row * SB + swz_chunk<SB>(row, h * 4 + g) * 16);
       }
 #pragma unroll
       for (int j = 0; j < FNW; ++j) {
         const int row = wn0 + 16 * j + l16;
-        fb[j] = *reinterpret_cast<const i4v *>(Bs + row * kStageBytes +
-                                               swz_chunk(row, h * 4 + g) * 16);
+        fb[j] = *reinterpret_cast<const i4v *>(Bs + row * SB + swz_chunk<SB>(row, h * 4 + g) * 16);
       }
 #pragma unroll
       for (int i = 0; i < FMW; ++i)
@@ -585,8 +592,7 @@ split_gemm_dma_kernel(SplitArgs a, int tiles_m, int tiles_n) {
         for (int j = 0; j < FNW; ++j) acc[i][j] = M::mma(fa[i], fb[j], acc[i][j]);
     }
     const bool seg_last = cur.st + 1 == seg_len(cur.seg, a);
-    if (M::CHUNK_STAGES > 0 && ((cur.st + 1) % (M::CHUNK_STAGES > 0 ? M::CHUNK_STAGES : 1) == 0 ||
-                                seg_last)) {
+    if (CHUNK > 0 && ((cur.st + 1) % (CHUNK > 0 ? CHUNK : 1) == 0 || seg_last)) {
 #pragma unroll
       for (int i = 0; i < FMW; ++i)
 #pragma unroll
@@ -632,12 +638,15 @@ int launch_split_t(const SplitArgs &a, const SplitLayout &L, hipStream_t s) {
   return MG_OK;
 }
 
-template <int ALGO, int WGM, int WGN, int FMW, int FNW, int NS>
-int launch_split_dma_t(const SplitArgs &a, const SplitLayout &L, hipStream_t s) {
-  typedef SplitDmaShape<WGM, WGN, FMW, FNW, NS> S;
-  auto kern = split_gemm_dma_kernel<ALGO, WGM, WGN, FMW, FNW, NS>;
+template <int ALGO, int WGM, int WGN, int FMW, int FNW, int NS, int SB>
+int launch_split_dma_t(const SplitArgs &a128, const SplitLayout &L, hipStream_t s) {
+  typedef SplitDmaShape<WGM, WGN, FMW, FNW, NS, SB> S;
+  auto kern = split_gemm_dma_kernel<ALGO, WGM, WGN, FMW, FNW, NS, SB>;
   static int once = ensure_lds(kern, S::LDS_BYTES);
   if (once != MG_OK) return once;
+  SplitArgs a = a128;  // stage counts in SB-byte stages
+  a.total_stages = a128.total_stages * (kStageBytes / SB);
+  a.seg_stages = a128.seg_stages * (kStageBytes / SB);
   const int tiles_m = (int)(L.mp / S::BM), tiles_n = (int)(L.np / S::BN);
   hipLaunchKernelGGL(kern, dim3(tiles_m * tiles_n), dim3(S::THREADS), S::LDS_BYTES, s, a, tiles_m,
                      tiles_n);
@@ -645,10 +654,11 @@ int launch_split_dma_t(const SplitArgs &a, const SplitLayout &L, hipStream_t s) 
   return MG_OK;
 }
 
-template <int WGM, int WGN, int FMW, int FNW, int NS>
+template <int WGM, int WGN, int FMW, int FNW, int NS, int SB = 128>
 int launch_split_dma(int algo, const SplitArgs &a, const SplitLayout &L, hipStream_t s) {
-  return algo == MG_SPLIT_BF16 ? launch_split_dma_t<MG_SPLIT_BF16, WGM, WGN, FMW, FNW, NS>(a, L, s)
-                               : launch_split_dma_t<MG_SPLIT_I8, WGM, WGN, FMW, FNW, NS>(a, L, s);
+  return algo == MG_SPLIT_BF16
+             ? launch_split_dma_t<MG_SPLIT_BF16, WGM, WGN, FMW, FNW, NS, SB>(a, L, s)
+             : launch_split_dma_t<MG_SPLIT_I8, WGM, WGN, FMW, FNW, NS, SB>(a, L, s);
 }
 
 template <int WGM, int WGN, int FMW, int FNW>
@@ -742,13 +752,15 @@ int split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, const d
   return MG_OK;
 }
 
-int split_num_cfgs() { return 6; }
+int split_num_cfgs() { return 9; }
 
 // Product-kernel work division (measured on MI355X at n = 4096): the 256x256
 // direct-to-LDS tile once every CU gets one, then the 128x256 one, else the
 // register-staged 128x128 tile.
-int split_pick_cfg(int64_t mp, int64_t np) {
-  if ((mp / 256) * (np / 256) >= 256) return 4;
+int split_pick_cfg(int algo, int64_t mp, int64_t np) {
+  // INT8: the 16-wave 256x256 tile once it fills the chip; BF16 keeps its
+  // FP32 chunk accumulators in registers and runs best with 8 waves.
+  if (algo == MG_SPLIT_I8 && (mp / 256) * (np / 256) >= 256) return 4;
   if ((mp / 128) * (np / 256) >= 256) return 2;
   return 0;
 }
@@ -789,7 +801,7 @@ int split_multiply(int algo, int slices, int64_t m, int64_t n, int64_t k, double
   a.seg_stages = (int)std::min<int64_t>(seg_stages, a.total_stages);
   a.alpha = alpha;
   a.beta = beta;
-  if (cfg < 0) cfg = split_pick_cfg(L.mp, L.np);
+  if (cfg < 0) cfg = split_pick_cfg(algo, L.mp, L.np);
   switch (cfg) {
     case 0: return launch_split<2, 2, 4, 4>(algo, a, L, s);          // 128x128, 4 waves, registers
     case 1: return launch_split_dma<2, 2, 4, 4, 4>(algo, a, L, s);   // 128x128, 4 waves, ring of 4
@@ -797,6 +809,9 @@ int split_multiply(int algo, int slices, int64_t m, int64_t n, int64_t k, double
     case 3: return launch_split_dma<2, 2, 8, 4, 3>(algo, a, L, s);   // 256x128, 4 waves, ring of 3
     case 4: return launch_split_dma<4, 4, 4, 4, 2>(algo, a, L, s);   // 256x256, 16 waves, ring of 2
     case 5: return launch_split_dma<2, 4, 4, 4, 2>(algo, a, L, s);   // 128x256, 8 waves, ring of 2
+    case 6: return launch_split_dma<2, 4, 8, 4, 4, 64>(algo, a, L, s);  // 256x256, 8 waves, 4 x 64 B
+    case 7: return launch_split_dma<4, 4, 4, 4, 4, 64>(algo, a, L, s);  // 256x256, 16 waves, 4 x 64 B
+    case 8: return launch_split_dma<2, 4, 4, 4, 6, 64>(algo, a, L, s);  // 128x256, 8 waves, 6 x 64 B
   }
   set_error("unknown split cfg %d", cfg);
   return MG_ERR_INVALID_ARG;

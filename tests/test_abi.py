@@ -103,7 +103,7 @@ def test_split_layout_and_errors():
     assert L["total_bytes"] >= L["p_off"] + 8 * 256 * 512
     Lb = mg.split_layout(mg.SPLIT_BF16, 6, 1, 1, 1)
     assert (Lb["mp"], Lb["np"], Lb["kp"], Lb["elem_bytes"]) == (256, 256, 128, 2)
-    assert mg.split_num_cfgs() == 6
+    assert mg.split_num_cfgs() == 9
     assert mg.split_default_slices(mg.SPLIT_I8) == 7
     assert mg.split_default_slices(mg.SPLIT_BF16) == 6
     with pytest.raises(mg.MgError):

@@ -228,7 +228,7 @@ def test_workspace_below_operands_is_not_an_overlap():
 
 
 @pytest.mark.parametrize("kind", ["i8", "bf16"])
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("cfg", list(range(9)))
 def test_split_work_divisions_bit_exact(kind, cfg):
     """Every work division of the product kernel gives the oracle's bits."""
     algo = ALGOS[kind]

@@ -108,6 +108,26 @@ def time_launches(fn, steps, warmup, stream):
     return [s.elapsed_time(e) for s, e in ev], wall
 
 
+def time_interleaved(fns, steps, warmup, stream):
+    """Per-launch durations (ms) of several launchers timed in rotation (one
+    launch of each per round), so that clock drift affects all alike."""
+    import torch
+    for _ in range(warmup):
+        for fn in fns:
+            fn()
+    torch.cuda.synchronize()
+    out = [[] for _ in fns]
+    for _ in range(steps):
+        for i, fn in enumerate(fns):
+            s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s.record(stream)
+            fn()
+            e.record(stream)
+            out[i].append((s, e))
+    torch.cuda.synchronize()
+    return [[s.elapsed_time(e) for s, e in evs] for evs in out]
+
+
 def bench_native(n, steps, warmup):
     import torch
     import paper_1602_08477_amd as mg
@@ -142,6 +162,53 @@ def bench_native(n, steps, warmup):
     del dA, dB, dC, C0
     torch.cuda.empty_cache()
     return ms_per_step, kern_ms, err
+
+
+def bench_sizes(steps, warmup):
+    """The square size sweep (n = 512 with alpha = 1.5, beta = 0.5; n = 1024 ...
+    4096 and (8192, 1024, 4096) with alpha = beta = 1), default work division:
+    median kernel time from HIP events, warm operands; for n <= 2048 also a
+    cold time with the L2 and MALL flushed by a 512 MiB write before each
+    launch."""
+    import torch
+    import paper_1602_08477_amd as mg
+    import synth
+    stream = torch.cuda.current_stream()
+    flush = torch.empty(1 << 26, dtype=torch.float64, device="cuda")
+    out = []
+    cases = [((512, 512, 512), 1.5, 0.5, 1)] + [((n, n, n), 1.0, 1.0, 2)
+                                                for n in (1024, 2048, 4096)]
+    cases.append(((8192, 1024, 4096), 1.0, 1.0, 2))
+    for (m, n, k), alpha, beta, cfg_id in cases:
+        seed = synth.config_seed(cfg_id)
+        dA = synth.matrix(seed, synth.STREAM_A, m, k, device="cuda")
+        dB = synth.matrix(seed, synth.STREAM_B, k, n, device="cuda")
+        dC = synth.matrix(seed, synth.STREAM_C, m, n, device="cuda")
+        fn = lambda: mg.gemm(dA, dB, dC, alpha, beta)  # noqa: E731
+        reps = max(steps, 20)
+        per, _ = time_launches(fn, reps, warmup, stream)
+        ms = float(np.median(per))
+        flop = 2.0 * m * n * k
+        rec = {"m": m, "n": n, "k": k, "alpha": alpha, "beta": beta,
+               "tile_cfg": mg.pick_tile_cfg(m, n, k), "ms": round(ms, 5),
+               "tflops": round(flop / ms / 1e9, 3),
+               "pct_peak": round(100 * flop / ms / 1e9 / FP64_PEAK, 2)}
+        if max(m, n, k) <= 2048:
+            cold = []
+            for _ in range(reps):
+                flush.fill_(1.0)
+                s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                s.record(stream)
+                fn()
+                e.record(stream)
+                torch.cuda.synchronize()
+                cold.append(s.elapsed_time(e))
+            rec["ms_cold"] = round(float(np.median(cold)), 5)
+        out.append(rec)
+        del dA, dB, dC
+    del flush
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_split(n, steps, warmup):
@@ -222,9 +289,9 @@ def bench_batched(steps):
         plan = mg.Plan(code, probs, table)
         plan_h = mg.Plan(code, probs)  # heuristic table, for comparison
         stream = torch.cuda.current_stream()
-        per_g, _ = time_launches(lambda: plan.launch(graph=True), steps, 3, stream)
-        per_d, _ = time_launches(lambda: plan.launch(graph=False), steps, 3, stream)
-        per_h, _ = time_launches(lambda: plan_h.launch(graph=True), steps, 3, stream)
+        per_g, per_d, per_h = time_interleaved(
+            [lambda: plan.launch(graph=True), lambda: plan.launch(graph=False),
+             lambda: plan_h.launch(graph=True)], steps, 5, stream)
         ms = float(np.median(per_g))
         roof_ms, flop, byts = batched_roofline_ms(shapes, esz, peak)
         st = plan.stats()
@@ -242,38 +309,28 @@ def bench_batched(steps):
     return out
 
 
-def bench_serving(seconds, rate=2000.0):
-    """Open-loop Poisson arrivals, square n log-uniform in [32, 2048], 70 %
-    native FP64 / 30 % split-INT8, operands resident on the device, HBM cap
-    64 GiB; latency from each request's scheduled arrival to completion."""
-    import torch
-    import paper_1602_08477_amd as mg
-    import synth
-    seed = synth.config_seed(5)
-    count = int(rate * seconds)
+def serve_trace(mg, synth, seed, rate, seconds, pools, ring_ptr, ring, nmax, budget, table):
+    """One open-loop replay: Poisson arrivals at ``rate``, square n
+    log-uniform in [32, 2048], 70 % native / 30 % split-INT8, operands are
+    views of resident pools; returns latency percentiles and throughput."""
+    count = max(1, int(rate * seconds))
     gaps = synth.poisson_gaps(seed, synth.STREAM_ARRIVALS, count, rate)
     t_arr = np.cumsum(gaps) - gaps[0]
-    ns = synth.log_uniform_int(seed, synth.STREAM_SIZES, count, 32, 2048)
+    ns = synth.log_uniform_int(seed, synth.STREAM_SIZES, count, 32, nmax)
     mix = synth.uniform_unit(seed, synth.STREAM_MIX, count)
     algos = np.where(mix < 0.3, mg.SPLIT_I8, mg.NATIVE)
-    nmax = 2048
-    pool_elems = 1 << 26  # 512 MiB of U[-1,1) operands, requests read views of it
-    pool_a = synth.flat_uniform(seed, 0, pool_elems, device="cuda")
-    pool_b = synth.flat_uniform(seed, 1, pool_elems, device="cuda")
-    ring = 256
-    cbuf = torch.zeros(ring, nmax * nmax, dtype=torch.float64, device="cuda")
+    pool_a, pool_b, pool_elems = pools
     offs = synth.log_uniform_int(seed, 12, count, 1, pool_elems - nmax * nmax - 1) // 32 * 32
     reqs = (mg.Request * count)()
-    base_a, base_b, base_c = pool_a.data_ptr(), pool_b.data_ptr(), cbuf.data_ptr()
+    base_a, base_b = pool_a.data_ptr(), pool_b.data_ptr()
     for i in range(count):
         n = int(ns[i])
         o = int(offs[i]) * 8
         reqs[i] = mg.Request(mg.F64, int(algos[i]),
                              mg.Problem(n, n, n, 1.0, 1.0, base_a + o, n, base_b + o, n,
-                                        base_c + (i % ring) * nmax * nmax * 8, n),
+                                        ring_ptr + (i % ring) * nmax * nmax * 8, n),
                              int(t_arr[i] * 1e9))
-    table = mg.autotune(mg.F64, reps=2)
-    with mg.Server(n_streams=4, max_slots=ring, max_batch=64, hbm_budget_bytes=64 << 30,
+    with mg.Server(n_streams=4, max_slots=ring, max_batch=64, hbm_budget_bytes=budget,
                    table=table) as srv:
         res = srv.replay(reqs)
         st = srv.stats()
@@ -283,9 +340,8 @@ def bench_serving(seconds, rate=2000.0):
     t1 = max(r.t_done_ns for r in res if r.status == 0)
     flop = float(np.sum(2.0 * ns.astype(np.float64) ** 3 * ok))
     bsz = np.array([r.batch_size for r in res])[ok]
-    del cbuf, pool_a, pool_b
-    torch.cuda.empty_cache()
     return {"requests": count, "rate_per_s": rate, "seconds": seconds,
+            "hbm_budget_gib": round(budget / 2 ** 30, 3),
             "completed_ok": int(ok.sum()), "rejected_or_failed": int((~ok).sum()),
             "p50_ms": round(float(np.percentile(lat, 50)), 4),
             "p99_ms": round(float(np.percentile(lat, 99)), 4),
@@ -293,8 +349,37 @@ def bench_serving(seconds, rate=2000.0):
             "mean_ms": round(float(lat.mean()), 4),
             "delivered_tflops": round(flop / ((t1 - t0) / 1e9) / 1e12, 3),
             "mean_batch_size": round(float(bsz.mean()), 2), "batches": st["batches"],
-            "max_batch": st["max_batch_seen"], "max_inflight_gib": round(
-                st["max_inflight_bytes"] / 2 ** 30, 3)}
+            "max_batch": st["max_batch_seen"],
+            "max_inflight_gib": round(st["max_inflight_bytes"] / 2 ** 30, 3),
+            "max_slots_used": st["max_slots_used"]}
+
+
+def bench_serving(seconds, rate=2000.0):
+    """Open-loop Poisson serving at 2000 requests/s for ``seconds`` under a
+    64 GiB HBM budget; then the same mix under a 1 GiB budget (admission
+    binds), and a saturation sweep of higher arrival rates."""
+    import torch
+    import paper_1602_08477_amd as mg
+    import synth
+    nmax = 2048
+    pool_elems = 1 << 26  # 512 MiB of U[-1,1) operands, requests read views of it
+    seed = synth.config_seed(5)
+    pools = (synth.flat_uniform(seed, 0, pool_elems, device="cuda"),
+             synth.flat_uniform(seed, 1, pool_elems, device="cuda"), pool_elems)
+    ring = 256
+    cbuf = torch.zeros(ring, nmax * nmax, dtype=torch.float64, device="cuda")
+    table = mg.autotune(mg.F64, reps=2)
+    args = (pools, cbuf.data_ptr(), ring, nmax)
+    out = serve_trace(mg, synth, seed, rate, seconds, *args, 64 << 30, table)
+    short = min(seconds, 10.0)
+    out["stress_1gib"] = serve_trace(mg, synth, synth.config_seed(5, 1), rate, short, *args,
+                                     1 << 30, table)
+    out["saturation"] = [serve_trace(mg, synth, synth.config_seed(5, 2 + i), r,
+                                     min(seconds, 3.0), *args, 64 << 30, table)
+                         for i, r in enumerate((8000.0, 16000.0, 32000.0))]
+    del cbuf, pools
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(n, target_s=12.0):
@@ -316,9 +401,24 @@ def cpu_baseline(n, target_s=12.0):
             break
         rows = min(n, rows * 2 if dt < target_s / 16 else rows * 4)
     tflops = 2.0 * rows * n * n / dt / 1e12
-    return {"value": float(f"{tflops:.6g}"), "unit": "TFLOP/s", "cores": oracle.threads(),
+    cores = oracle.threads()
+    # The whole small workloads, on all cores and on one core.
+    small = {}
+    for sn in (512, 1024):
+        sd = synth.config_seed(1 if sn == 512 else 2)
+        A = synth.matrix(sd, synth.STREAM_A, sn, sn)
+        Bs = synth.matrix(sd, synth.STREAM_B, sn, sn)
+        C = synth.matrix(sd, synth.STREAM_C, sn, sn)
+        for tag, th in (("all_cores", cores), ("1_core", 1)):
+            oracle.set_threads(th)
+            t0 = time.perf_counter()
+            oracle.dgemm(1.0, A, Bs, 1.0, C)
+            small[f"n{sn}_{tag}_gflops"] = round(2.0 * sn ** 3 / (time.perf_counter() - t0) / 1e9, 3)
+    oracle.set_threads(cores)
+    return {"value": float(f"{tflops:.6g}"), "unit": "TFLOP/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{rows} of {n} output rows of the n={n} FP64 GEMM ({dt:.1f} s)"}
+            "sample": f"{rows} of {n} output rows of the n={n} FP64 GEMM ({dt:.1f} s)",
+            "small_workloads": small}
 
 
 def main():
@@ -328,7 +428,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--quick", action="store_true", help="headline only (for profiling)")
-    ap.add_argument("--leg", choices=["split", "batched", "serving"], default=None,
+    ap.add_argument("--leg", choices=["sizes", "split", "batched", "serving"], default=None,
                     help="run only this secondary leg and print its record (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
@@ -349,6 +449,7 @@ def main():
         sys.exit(3)
     if args.leg is not None:
         fn = {"split": lambda: bench_split(4096, max(3, args.steps), 1),
+              "sizes": lambda: bench_sizes(args.steps, args.warmup),
               "batched": lambda: bench_batched(max(3, args.steps)),
               "serving": lambda: bench_serving(args.serve_seconds)}[args.leg]
         print(json.dumps({"leg": args.leg, "record": fn()}), flush=True)
@@ -393,6 +494,8 @@ def main():
                      "kernel_ms": round(kern_ms, 4)},
     }
     if not args.quick:
+        eprint("bench: size sweep")
+        rec["sizes"] = bench_sizes(args.steps, args.warmup)
         eprint("bench: split precision n=4096")
         rec["split"] = bench_split(4096, max(5, args.steps), 2)
         eprint("bench: batched 2000 problems")

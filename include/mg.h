@@ -215,10 +215,12 @@ int mg_grouped_class_info(int cls, int *bm, int *bn);
 int mg_tune_bucket(int64_t m, int64_t n, int64_t k);
 /* Heuristic table (largest tile wasting at most a quarter of its area). */
 int mg_tune_default(int dtype, mg_tune_table *out);
-/* Autotuner: for every bucket, times each tile class on a batch of 48
- * problems of the bucket's representative shape (reps launches on `stream`,
- * HIP events) and records the fastest.  Allocates and frees its own scratch
- * operands; blocks until done. */
+/* Autotuner: for every bucket, times each tile class on a batch of problems
+ * of the bucket's representative shape, as many (48 to 4096) as it takes for
+ * the largest class to give every workgroup slot of the persistent kernel
+ * four tiles, so that classes compete on throughput in a full batch (reps
+ * launches on `stream`, HIP events), and records the fastest.  Allocates and
+ * frees its own scratch operands (about 0.4 GB for FP64); blocks until done. */
 int mg_autotune(int dtype, int reps, void *stream, mg_tune_table *out);
 
 /* Builds a plan (host work list + device copy; blocks while uploading).

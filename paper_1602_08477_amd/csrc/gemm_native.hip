@@ -40,7 +40,8 @@ struct CfgDesc {
 constexpr CfgDesc kCfgs[] = {{128, 128, 2, 2, 1}, {128, 64, 2, 2, 1}, {64, 64, 2, 2, 1},
                              {64, 32, 2, 2, 1},   {32, 32, 2, 2, 1},  {128, 128, 4, 2, 1},
                              {128, 128, 2, 4, 1}, {64, 64, 2, 2, 2},  {128, 64, 4, 2, 1},
-                             {128, 64, 2, 2, 2}};
+                             {128, 64, 2, 2, 2},  {256, 128, 4, 2, 1}, {128, 256, 2, 4, 1},
+                             {256, 128, 4, 4, 1}, {128, 128, 4, 2, 2}};
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
 template <typename T, int BM, int BN, bool VEC_OK, int WGM = 2, int WGN = 2, int BKM = 1>
@@ -79,6 +80,10 @@ int launch_cfg(int cfg, const GemmArgs<T> &g, hipStream_t s) {
     case 7: return launch_one<T, 64, 64, VEC_OK, 2, 2, 2>(g, s);
     case 8: return launch_one<T, 128, 64, VEC_OK, 4, 2, 1>(g, s);
     case 9: return launch_one<T, 128, 64, VEC_OK, 2, 2, 2>(g, s);
+    case 10: return launch_one<T, 256, 128, VEC_OK, 4, 2, 1>(g, s);
+    case 11: return launch_one<T, 128, 256, VEC_OK, 2, 4, 1>(g, s);
+    case 12: return launch_one<T, 256, 128, VEC_OK, 4, 4, 1>(g, s);
+    case 13: return launch_one<T, 128, 128, VEC_OK, 4, 2, 2>(g, s);
   }
   set_error("unknown tile cfg %d", cfg);
   return MG_ERR_INVALID_ARG;

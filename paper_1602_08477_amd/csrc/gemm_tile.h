@@ -122,63 +122,106 @@ __device__ __forceinline__ double dpp_swap1(double x) {
   return __hiloint2double(hi2, lo2);
 }
 
-// C tile epilogue for one 16x16 block: out = alpha*acc + beta*C (C unread
-// when beta == 0).  Lane l holds column l%16 of rows row_of(l/16, r).  FP64:
-// neighbouring lanes (same rows, columns j and j+1) swap one value each so
-// that each lane writes a 16-byte pair of adjacent columns of one row.
+// C tile epilogue for a wave's FM x FN grid of 16x16 blocks whose top-left
+// output is (row0, col0): out = alpha*acc + beta*C (C unread when beta == 0).
+// In block (i, j), lane l holds column l%16 of rows row_of(l/16, r).  One
+// block row i at a time, all its C loads are issued before its first store,
+// so they are in flight together instead of each waiting behind the previous
+// store (and the extra registers stay at one block row's worth).
+// FP64: neighbouring lanes (same rows, columns c and c+1) swap one value each
+// so that each lane owns a 16-byte pair of adjacent columns of one row.
 template <typename T, bool VEC_OK>
 struct Epilogue;
 
 template <bool VEC_OK>
 struct Epilogue<double, VEC_OK> {
-  __device__ static __forceinline__ void store(const GemmArgs<double> &g, d4v acc, int row0,
-                                               int col0, int lane) {
+  template <int FM, int FN, int AM, int AN>
+  __device__ static __forceinline__ void store(const GemmArgs<double> &g,
+                                               const d4v (&acc)[AM][AN], int row0, int col0,
+                                               int lane) {
     const int gq = lane >> 4, j = lane & 15;
     const bool odd = j & 1;
-    const int col = col0 + (j & ~1);
+    const bool use_c = g.beta != 0.0;
 #pragma unroll
-    for (int r = 0; r < 4; r += 2) {
-      const double send = odd ? acc[r] : acc[r + 1];
-      const double got = dpp_swap1(send);
-      const int row = row0 + Mfma<double>::row_of(gq, r + (odd ? 1 : 0));
-      d2v v;
-      v[0] = odd ? got : acc[r];
-      v[1] = odd ? acc[r + 1] : got;
-      if (row >= g.m) continue;
-      double *p = g.C + (int64_t)row * g.ldc + col;
-      if (VEC_OK && col + 1 < g.n) {
-        d2v c = {0.0, 0.0};
-        if (g.beta != 0.0) c = *reinterpret_cast<const d2v *>(p);
-        d2v o;
-        o[0] = g.beta != 0.0 ? fma(g.alpha, v[0], g.beta * c[0]) : g.alpha * v[0];
-        o[1] = g.beta != 0.0 ? fma(g.alpha, v[1], g.beta * c[1]) : g.alpha * v[1];
-        *reinterpret_cast<d2v *>(p) = o;
-      } else {
+    for (int i = 0; i < FM; ++i) {
+      d2v v[FN][2], c[FN][2];
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          if (col + e < g.n) {
-            const double o = g.beta != 0.0 ? fma(g.alpha, v[e], g.beta * p[e]) : g.alpha * v[e];
-            p[e] = o;
+      for (int jb = 0; jb < FN; ++jb)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int r = 2 * h;
+          const double send = odd ? acc[i][jb][r] : acc[i][jb][r + 1];
+          const double got = dpp_swap1(send);
+          v[jb][h][0] = odd ? got : acc[i][jb][r];
+          v[jb][h][1] = odd ? acc[i][jb][r + 1] : got;
+        }
+#pragma unroll
+      for (int jb = 0; jb < FN; ++jb)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int row = row0 + 16 * i + Mfma<double>::row_of(gq, 2 * h + (odd ? 1 : 0));
+          const int col = col0 + 16 * jb + (j & ~1);
+          c[jb][h] = d2v{0.0, 0.0};
+          if (!use_c || row >= g.m) continue;
+          const double *p = g.C + (int64_t)row * g.ldc + col;
+          if (VEC_OK && col + 1 < g.n) {
+            c[jb][h] = *reinterpret_cast<const d2v *>(p);
+          } else {
+            if (col < g.n) c[jb][h][0] = p[0];
+            if (col + 1 < g.n) c[jb][h][1] = p[1];
           }
         }
-      }
+#pragma unroll
+      for (int jb = 0; jb < FN; ++jb)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int row = row0 + 16 * i + Mfma<double>::row_of(gq, 2 * h + (odd ? 1 : 0));
+          const int col = col0 + 16 * jb + (j & ~1);
+          if (row >= g.m) continue;
+          d2v o;
+#pragma unroll
+          for (int e = 0; e < 2; ++e)
+            o[e] = use_c ? fma(g.alpha, v[jb][h][e], g.beta * c[jb][h][e]) : g.alpha * v[jb][h][e];
+          double *p = g.C + (int64_t)row * g.ldc + col;
+          if (VEC_OK && col + 1 < g.n) {
+            *reinterpret_cast<d2v *>(p) = o;
+          } else {
+            if (col < g.n) p[0] = o[0];
+            if (col + 1 < g.n) p[1] = o[1];
+          }
+        }
     }
   }
 };
 
 template <bool VEC_OK>
 struct Epilogue<float, VEC_OK> {
-  __device__ static __forceinline__ void store(const GemmArgs<float> &g, f4v acc, int row0,
-                                               int col0, int lane) {
+  template <int FM, int FN, int AM, int AN>
+  __device__ static __forceinline__ void store(const GemmArgs<float> &g,
+                                               const f4v (&acc)[AM][AN], int row0, int col0,
+                                               int lane) {
     const int gq = lane >> 4, j = lane & 15;
-    const int col = col0 + j;
-    if (col >= g.n) return;
+    const bool use_c = g.beta != 0.0f;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = row0 + Mfma<float>::row_of(gq, r);
-      if (row >= g.m) continue;
-      float *p = g.C + (int64_t)row * g.ldc + col;
-      *p = g.beta != 0.0f ? fmaf(g.alpha, acc[r], g.beta * *p) : g.alpha * acc[r];
+    for (int i = 0; i < FM; ++i) {
+      float c[FN][4];
+#pragma unroll
+      for (int jb = 0; jb < FN; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = row0 + 16 * i + Mfma<float>::row_of(gq, r), col = col0 + 16 * jb + j;
+          c[jb][r] = 0.0f;
+          if (use_c && row < g.m && col < g.n) c[jb][r] = g.C[(int64_t)row * g.ldc + col];
+        }
+#pragma unroll
+      for (int jb = 0; jb < FN; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = row0 + 16 * i + Mfma<float>::row_of(gq, r), col = col0 + 16 * jb + j;
+          if (row < g.m && col < g.n)
+            g.C[(int64_t)row * g.ldc + col] =
+                use_c ? fmaf(g.alpha, acc[i][jb][r], g.beta * c[jb][r]) : g.alpha * acc[i][jb][r];
+        }
     }
   }
 };
@@ -293,11 +336,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &g, int m0, int n0, 
     __syncthreads();
   }
 
-#pragma unroll
-  for (int i = 0; i < S::FM; ++i)
-#pragma unroll
-    for (int j = 0; j < S::FN; ++j)
-      Epilogue<T, VEC_OK>::store(g, acc[i][j], m0 + wm0 + 16 * i, n0 + wn0 + 16 * j, lane);
+  Epilogue<T, VEC_OK>::template store<S::FM, S::FN>(g, acc, m0 + wm0, n0 + wn0, lane);
 }
 
 }  // namespace mg

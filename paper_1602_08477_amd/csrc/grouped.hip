@@ -39,7 +39,7 @@ template <typename T>
 struct GTileRec {
   GemmArgs<T> g;
   int tm, tn;
-  int cls;  // class | (vec_ok << 4)
+  int cls;  // class | (A, B, C 16-byte rows << 4) | (C 16-byte rows << 5)
   int pad;
 };
 
@@ -98,10 +98,326 @@ __global__ __launch_bounds__(kTileThreads, 3) void grouped_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Persistent kernel with a ring of direct global->LDS loads.
+//
+// Each workgroup walks its tiles (b, b+G, ...) as one stream of k-steps.  A
+// load cursor runs NS-1 steps ahead of the compute cursor and fills an
+// NS-stage LDS ring with global_load_lds (4 bytes per lane, so any leading
+// dimension and any element alignment is accepted), across tile boundaries:
+// the first k-steps of the next tile arrive while the current tile finishes.
+// No staging registers are used, which leaves room for two workgroups per CU.
+//
+// Edges: rows past m and columns past n are read from clamped in-bounds
+// addresses and never stored; k past the problem's k is read from a clamped
+// address and zeroed on both operands before the multiply.
+//
+// LDS stage: A block [BM rows][128 B] (BK = 128 B of k per step), its 16-byte
+// chunks XOR-swizzled per row so that the fragment reads of 16 rows hit
+// distinct banks; B block [BK/VEC][BN][VEC]: the VEC consecutive k of one
+// column form one 16-byte chunk, so a lane reads the B values of VEC MFMAs
+// with one 16-byte load and 16 lanes read 256 contiguous bytes.
+constexpr int kGdStageA = 64 * 128;
+constexpr int kGdStageB = 8192;
+constexpr int kGdStage = kGdStageA + kGdStageB;
+constexpr int kGdNS = 3;
+
+__device__ __forceinline__ int gd_bm(int cls) { return cls == 2 ? 32 : 64; }
+__device__ __forceinline__ int gd_bn(int cls) { return cls == 0 ? 64 : 32; }
+
+// Physical 16-byte chunk of logical chunk c in A row `row`.
+__device__ __forceinline__ int gd_swz_a(int row, int c) { return c ^ ((row >> 1) & 7); }
+
+template <int N>
+__device__ __forceinline__ void gd_wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// Waits until at most 4*q vector memory operations of this wave are pending.
+__device__ __forceinline__ void gd_wait_dyn(int q) {
+  switch (q) {
+    case 0: gd_wait_vmcnt<0>(); break;
+    case 1: gd_wait_vmcnt<4>(); break;
+    case 2: gd_wait_vmcnt<8>(); break;
+    case 3: gd_wait_vmcnt<12>(); break;
+    case 4: gd_wait_vmcnt<16>(); break;
+    case 5: gd_wait_vmcnt<20>(); break;
+    case 6: gd_wait_vmcnt<24>(); break;
+    case 7: gd_wait_vmcnt<28>(); break;
+    default: gd_wait_vmcnt<32>(); break;
+  }
+}
+
+__device__ __forceinline__ void gd_dma4(const void *src, unsigned char *lds_dst) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds_dst, 4, 0,
+                                   0);
+}
+
+// This lane's source addresses of one tile for every DMA slot, without the
+// k offset of the step: slot u of A covers tile row 2q + lane/32 (q = wave*ia
+// + u), slot u of B covers LDS bytes [256q, 256q + 256) of the B block.
+// Rows past m and columns past n are clamped to the last valid one.
+template <typename T>
+struct GdSlots {
+  const char *a[8];
+  const char *b[8];
+  int ia, ib;
+};
+
+template <typename T>
+__device__ __forceinline__ int gd_a_kofs(int wave, int ia, int u, int lane) {
+  constexpr int ESZ = sizeof(T), VEC = 16 / ESZ;
+  const int row = 2 * (wave * ia + u) + (lane >> 5);
+  return gd_swz_a(row, (lane & 31) >> 2) * VEC + ((lane & 3) * 4) / ESZ;
+}
+
+// B block byte o = ((kc*bn + col)*VEC + e)*size + (4-byte half): slot u of a
+// wave covers o in [256q, 256q + 256), q = wave*ib + u, lane at 4*lane.
+template <typename T>
+__device__ __forceinline__ int gd_b_krow(int wave, int ib, int u, int lane, int bn) {
+  constexpr int ESZ = sizeof(T), VEC = 16 / ESZ;
+  const int o = (wave * ib + u) * 256 + lane * 4;
+  return (o >> 4) / bn * VEC + (o & 15) / ESZ;  // kc*VEC + e
+}
+
+template <typename T>
+__device__ __forceinline__ int gd_b_col(int wave, int ib, int u, int lane, int bn) {
+  const int o = (wave * ib + u) * 256 + lane * 4;
+  return (o >> 4) & (bn - 1);
+}
+
+template <typename T>
+__device__ __forceinline__ void gd_setup(GdSlots<T> &sl, const GemmArgs<T> &g, int cls, int m0,
+                                         int n0, int wave, int lane) {
+  constexpr int ESZ = sizeof(T);
+  const int bm = gd_bm(cls), bn = gd_bn(cls);
+  sl.ia = bm / 8;
+  sl.ib = bn / 8;
+  const int boff = ((lane & 3) * 4) % ESZ;  // 4-byte half of an FP64 element
+  const char *A = reinterpret_cast<const char *>(g.A);
+  const char *B = reinterpret_cast<const char *>(g.B);
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int row = 2 * (wave * sl.ia + u) + (lane >> 5);
+    const int gr = min(m0 + row, g.m - 1);
+    sl.a[u] = A + ((int64_t)gr * g.lda + gd_a_kofs<T>(wave, sl.ia, u, lane)) * ESZ + boff;
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int col = gd_b_col<T>(wave, sl.ib, u, lane, bn);
+    const int gc = min(n0 + col, g.n - 1);
+    sl.b[u] = B + ((int64_t)gd_b_krow<T>(wave, sl.ib, u, lane, bn) * g.ldb + gc) * ESZ + boff;
+  }
+}
+
+// Issues this wave's share of the k-step at `kbase` (A and B blocks) into
+// `stage`; returns the number of DMA instructions issued (a multiple of 4).
+// Whole steps add one uniform offset per slot; the last, partial step of a
+// tile clamps k to the problem's last column of A / row of B.
+template <typename T>
+__device__ __forceinline__ int gd_issue(const GdSlots<T> &sl, const GemmArgs<T> &g, int cls,
+                                        int kbase, unsigned char *stage, int wave, int lane) {
+  constexpr int ESZ = sizeof(T), BK = 128 / ESZ;
+  const int64_t bstep = (int64_t)kbase * g.ldb * ESZ;
+  if (kbase + BK <= g.k) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (u < sl.ia) gd_dma4(sl.a[u] + (int64_t)kbase * ESZ, stage + (wave * sl.ia + u) * 256);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (u < sl.ib) gd_dma4(sl.b[u] + bstep, stage + kGdStageA + (wave * sl.ib + u) * 256);
+  } else {
+    const int klast = g.k - 1;
+    const int bn = gd_bn(cls);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (u < sl.ia) {
+        const int ko = gd_a_kofs<T>(wave, sl.ia, u, lane);
+        gd_dma4(sl.a[u] + (int64_t)(min(kbase + ko, klast) - ko) * ESZ,
+                stage + (wave * sl.ia + u) * 256);
+      }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (u < sl.ib) {
+        const int kr = gd_b_krow<T>(wave, sl.ib, u, lane, bn);
+        gd_dma4(sl.b[u] + (int64_t)(min(kbase + kr, klast) - kr) * g.ldb * ESZ,
+                stage + kGdStageA + (wave * sl.ib + u) * 256);
+      }
+  }
+  return sl.ia + sl.ib;
+}
+
+// One k-step of a BM x BN tile from an LDS stage.  TAIL: only the first
+// `kvalid` k of the step belong to the problem; the rest is zeroed on both
+// operands (values read from clamped addresses never reach the sums).
+template <typename T, int BM, int BN, bool TAIL>
+__device__ __forceinline__ void gd_compute(typename Mfma<T>::acc_t (&acc)[2][2],
+                                           const unsigned char *As, const unsigned char *Bs,
+                                           int wave, int lane, int kvalid) {
+  typedef Mfma<T> M;
+  typedef typename M::vec_t V;
+  constexpr int ESZ = sizeof(T), VEC = 16 / ESZ;
+  constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+  const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
+  const int g = lane >> 4, l16 = lane & 15;
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int kc = 4 * r + g;
+    V a[FM];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+      const int row = wm0 + 16 * i + l16;
+      a[i] = *reinterpret_cast<const V *>(As + row * 128 + gd_swz_a(row, kc) * 16);
+      if (TAIL) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) a[i][v] = kc * VEC + v < kvalid ? a[i][v] : T(0);
+      }
+    }
+    V b[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      b[j] = *reinterpret_cast<const V *>(Bs + (kc * BN + wn0 + 16 * j + l16) * 16);
+      if (TAIL) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) b[j][v] = kc * VEC + v < kvalid ? b[j][v] : T(0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < VEC; ++v)
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = M::mma(a[i][v], b[j][v], acc[i][j]);
+  }
+}
+
+template <typename T, int BM, int BN>
+__device__ __forceinline__ void gd_step(typename Mfma<T>::acc_t (&acc)[2][2],
+                                        const unsigned char *As, const unsigned char *Bs,
+                                        int wave, int lane, int kvalid) {
+  if (kvalid >= 128 / (int)sizeof(T)) gd_compute<T, BM, BN, false>(acc, As, Bs, wave, lane, kvalid);
+  else gd_compute<T, BM, BN, true>(acc, As, Bs, wave, lane, kvalid);
+}
+
+template <typename T, int BM, int BN>
+__device__ __forceinline__ void gd_store(const GTileRec<T> &t,
+                                         const typename Mfma<T>::acc_t (&acc)[2][2], int wave,
+                                         int lane) {
+  constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+  const int m0 = t.tm * BM + (wave >> 1) * WM, n0 = t.tn * BN + (wave & 1) * WN;
+  if ((t.cls >> 5) & 1) Epilogue<T, true>::template store<FM, FN>(t.g, acc, m0, n0, lane);
+  else Epilogue<T, false>::template store<FM, FN>(t.g, acc, m0, n0, lane);
+}
+
+// Tile record through the constant address space: the list is never written
+// during the launch, so the uniform record loads become scalar loads, which
+// do not count against the vector-memory counter the DMA ring waits on.
+template <typename T>
+__device__ __forceinline__ GTileRec<T> gd_record(const GTileRec<T> *tiles, int w) {
+  typedef __attribute__((address_space(4))) const GTileRec<T> CRec;
+  GTileRec<T> r;
+  __builtin_memcpy(&r, (const GTileRec<T> *)&((const CRec *)tiles)[w], sizeof(r));
+  return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTileThreads, 3) void grouped_dma_kernel(
+    const GTileRec<T> *__restrict__ tiles, int ntiles) {
+  typedef typename Mfma<T>::acc_t Acc;
+  constexpr int BK = 128 / (int)sizeof(T);
+  extern __shared__ __align__(16) unsigned char lds[];
+  // wave index made uniform so LDS destinations (M0) are scalar arithmetic
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int G = (int)gridDim.x;
+
+  // Load cursor: tile index, record, next k-step; scale-only tiles have no steps.
+  int lw = blockIdx.x, lkt = 0;
+  GTileRec<T> L{};
+  if (lw < ntiles) L = gd_record(tiles, lw);
+  while (lw < ntiles && (L.cls & 15) == kScaleCls) {
+    lw += G;
+    if (lw < ntiles) L = gd_record(tiles, lw);
+  }
+  GdSlots<T> sl;
+  if (lw < ntiles) {
+    const int c = L.cls & 15;
+    gd_setup<T>(sl, L.g, c, L.tm * gd_bm(c), L.tn * gd_bn(c), wave, lane);
+  }
+  // Pending steps: DMA counts/4 in 4-bit fields, oldest lowest; their sum.
+  unsigned pend = 0;
+  int nfl = 0, psum = 0, li = 0;
+  auto issue_next = [&]() {
+    if (lw >= ntiles) return;
+    const int cnt = gd_issue<T>(sl, L.g, L.cls & 15, lkt * BK, lds + (li % kGdNS) * kGdStage,
+                                wave, lane);
+    pend |= (unsigned)(cnt >> 2) << (4 * nfl);
+    ++nfl;
+    psum += cnt >> 2;
+    ++li;
+    if (++lkt * BK >= L.g.k) {
+      lkt = 0;
+      do {
+        lw += G;
+        if (lw < ntiles) L = gd_record(tiles, lw);
+      } while (lw < ntiles && (L.cls & 15) == kScaleCls);
+      if (lw < ntiles) {
+        const int c = L.cls & 15;
+        gd_setup<T>(sl, L.g, c, L.tm * gd_bm(c), L.tn * gd_bn(c), wave, lane);
+      }
+    }
+  };
+#pragma unroll
+  for (int q = 0; q < kGdNS - 1; ++q) issue_next();
+
+  Acc acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = Acc{};
+
+  int cw = blockIdx.x, ckt = 0, t = 0;
+  GTileRec<T> C{};
+  if (cw < ntiles) C = gd_record(tiles, cw);
+  for (;;) {
+    while (cw < ntiles && (C.cls & 15) == kScaleCls) {
+      scale_tile<T>(C.g, C.tm * kScaleTile, C.tn * kScaleTile);
+      cw += G;
+      if (cw < ntiles) C = gd_record(tiles, cw);
+    }
+    if (cw >= ntiles) break;
+    // Step t has landed once only the later steps' DMAs may still be pending.
+    gd_wait_dyn(psum - (int)(pend & 15));
+    __builtin_amdgcn_s_barrier();
+    issue_next();
+    const unsigned char *As = lds + (t % kGdNS) * kGdStage;
+    const unsigned char *Bs = As + kGdStageA;
+    const int c = C.cls & 15, kvalid = C.g.k - ckt * BK;
+    if (c == 0) gd_step<T, 64, 64>(acc, As, Bs, wave, lane, kvalid);
+    else if (c == 1) gd_step<T, 64, 32>(acc, As, Bs, wave, lane, kvalid);
+    else gd_step<T, 32, 32>(acc, As, Bs, wave, lane, kvalid);
+    psum -= (int)(pend & 15);
+    pend >>= 4;
+    --nfl;
+    ++t;
+    if (++ckt * BK >= C.g.k) {
+      if (c == 0) gd_store<T, 64, 64>(C, acc, wave, lane);
+      else if (c == 1) gd_store<T, 64, 32>(C, acc, wave, lane);
+      else gd_store<T, 32, 32>(C, acc, wave, lane);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = Acc{};
+      ckt = 0;
+      cw += G;
+      if (cw < ntiles) C = gd_record(tiles, cw);
+    }
+  }
+}
+
 template <typename T>
 size_t grouped_lds_bytes() {
-  return std::max({TileShape<T, 64, 64>::LDS_BYTES, TileShape<T, 64, 32>::LDS_BYTES,
-                   TileShape<T, 32, 32>::LDS_BYTES});
+  return (size_t)kGdNS * kGdStage;
 }
 
 int bucket_of(int64_t x) {
@@ -193,11 +509,12 @@ int build_t(int64_t count, const mg_problem *probs, const mg_tune_table *table, 
     const bool vec = vec_aligned(q.A, q.lda, sizeof(T), VEC) &&
                      vec_aligned(q.B, q.ldb, sizeof(T), VEC) &&
                      vec_aligned(q.C, q.ldc, sizeof(T), VEC);
+    const bool c_vec = vec_aligned(q.C, q.ldc, sizeof(T), VEC);
     const int bm = kClsBM[cls], bn = kClsBN[cls];
     const int tm = (int)ceil_div(q.m, bm), tn = (int)ceil_div(q.n, bn);
     for (int a = 0; a < tm; ++a)
       for (int b = 0; b < tn; ++b) {
-        tiles.push_back(GTileRec<T>{g, a, b, cls | (vec ? 16 : 0), 0});
+        tiles.push_back(GTileRec<T>{g, a, b, cls | (vec ? 16 : 0) | (c_vec ? 32 : 0), 0});
         // MFMA work of the padded tile plus its operand traffic (in FLOP-equivalents)
         cost.push_back(2.0 * bm * bn * (double)round_up(q.k, Mfma<T>::BK) +
                        16.0 * (bm + bn) * (double)q.k);
@@ -240,11 +557,11 @@ int occupancy_t(int *cus, int *occ) {
     MG_HIP_TRY(hipGetDevice(&dev));
     MG_HIP_TRY(hipDeviceGetAttribute(&s_cus, hipDeviceAttributeMultiprocessorCount, dev));
     const size_t lds = grouped_lds_bytes<T>();
-    MG_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(grouped_kernel<T>),
+    MG_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(grouped_dma_kernel<T>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int o = 0;
     MG_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &o, reinterpret_cast<const void *>(grouped_kernel<T>), kTileThreads, lds));
+        &o, reinterpret_cast<const void *>(grouped_dma_kernel<T>), kTileThreads, lds));
     s_occ = std::max(1, o);
   }
   *cus = s_cus;
@@ -254,7 +571,7 @@ int occupancy_t(int *cus, int *occ) {
 
 template <typename T>
 int launch_t(const void *d_tiles, int ntiles, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(grouped_kernel<T>, dim3(grid), dim3(kTileThreads), grouped_lds_bytes<T>(), s,
+  hipLaunchKernelGGL(grouped_dma_kernel<T>, dim3(grid), dim3(kTileThreads), grouped_lds_bytes<T>(), s,
                      static_cast<const GTileRec<T> *>(d_tiles), ntiles);
   MG_HIP_TRY(hipGetLastError());
   return MG_OK;
@@ -320,7 +637,7 @@ int plan_launch(Plan *p, hipStream_t s, bool use_graph) {
   if (p->ntiles == 0) return MG_OK;
   if (!use_graph) return launch_raw(p, s);
   if (p->exec == nullptr) {
-    // Capture reset + persistent kernel once on a private stream.
+    // Capture the persistent launch once on a private stream.
     hipStream_t cap;
     MG_HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
@@ -365,8 +682,19 @@ namespace mg {
 
 namespace {
 
-constexpr int kTuneMaxExtent = 512;
-constexpr int kTuneProblems = 48;
+constexpr int kTuneMinProblems = 48;
+constexpr int kTuneMaxProblems = 4096;
+constexpr int kTuneWavesOfTiles = 4;          // tiles per workgroup slot when timing
+constexpr int64_t kTuneOperandElems = 1 << 24;  // per operand scratch (A, B)
+
+// Problems per bucket: enough that even the largest tile class gives every
+// workgroup slot several tiles, so a class is judged by its throughput in a
+// full batch rather than by the parallelism a few problems expose.
+int64_t tune_count(int64_t m, int64_t n, int grid) {
+  const int64_t t0 = ceil_div(m, kClsBM[0]) * ceil_div(n, kClsBN[0]);
+  const int64_t want = ceil_div((int64_t)kTuneWavesOfTiles * grid, t0);
+  return std::min<int64_t>(kTuneMaxProblems, std::max<int64_t>(kTuneMinProblems, want));
+}
 
 int time_plan(Plan *p, int reps, hipStream_t s, hipEvent_t e0, hipEvent_t e1, float *ms) {
   int rc = plan_launch(p, s, false);  // warm-up
@@ -386,10 +714,19 @@ int time_plan(Plan *p, int reps, hipStream_t s, hipEvent_t e0, hipEvent_t e1, fl
 
 int autotune(int dtype, int reps, hipStream_t s, mg_tune_table *out) {
   const size_t esz = dtype == MG_F64 ? 8 : 4;
-  const size_t mat = (size_t)kTuneMaxExtent * kTuneMaxExtent * esz;
+  int grid = 0;
+  int rc = grouped_grid(dtype, INT32_MAX, &grid, nullptr);
+  if (rc != MG_OK) return rc;
+  // C needs a private region per problem; A and B are carved round-robin
+  // from fixed scratch so that consecutive problems read different memory.
+  int64_t c_elems = 0;
+  for (int b = 0; b < kTuneEdges; ++b)
+    for (int c = 0; c < kTuneEdges; ++c) {
+      const int64_t m = tune_bucket_rep(b), n = tune_bucket_rep(c);
+      c_elems = std::max(c_elems, tune_count(m, n, grid) * round_up(m * n, 64));
+    }
   void *dA = nullptr, *dB = nullptr, *dC = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  int rc = MG_OK;
   auto cleanup = [&]() {
     if (dA) (void)hipFree(dA);
     if (dB) (void)hipFree(dB);
@@ -397,39 +734,49 @@ int autotune(int dtype, int reps, hipStream_t s, mg_tune_table *out) {
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
   };
-  if (hipMalloc(&dA, mat) != hipSuccess || hipMalloc(&dB, mat) != hipSuccess ||
-      hipMalloc(&dC, mat * kTuneProblems) != hipSuccess) {
+  const size_t op_bytes = (size_t)kTuneOperandElems * esz;
+  if (hipMalloc(&dA, op_bytes) != hipSuccess || hipMalloc(&dB, op_bytes) != hipSuccess ||
+      hipMalloc(&dC, (size_t)c_elems * esz) != hipSuccess) {
     cleanup();
     set_error("autotune: scratch allocation failed");
     return MG_ERR_NO_MEMORY;
   }
-  if (hipMemset(dA, 0, mat) != hipSuccess || hipMemset(dB, 0, mat) != hipSuccess ||
-      hipMemset(dC, 0, mat * kTuneProblems) != hipSuccess ||
+  if (hipMemset(dA, 0, op_bytes) != hipSuccess || hipMemset(dB, 0, op_bytes) != hipSuccess ||
+      hipMemset(dC, 0, (size_t)c_elems * esz) != hipSuccess ||
       hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     cleanup();
     set_error("autotune: scratch setup failed");
     return MG_ERR_HIP;
   }
   out->dtype = dtype;
-  std::vector<mg_problem> probs(kTuneProblems);
+  std::vector<mg_problem> probs;
   mg_tune_table forced;
   for (int bm = 0; bm < kTuneEdges && rc == MG_OK; ++bm)
     for (int bn = 0; bn < kTuneEdges && rc == MG_OK; ++bn)
       for (int bk = 0; bk < kTuneEdges && rc == MG_OK; ++bk) {
         const int64_t m = tune_bucket_rep(bm), n = tune_bucket_rep(bn), k = tune_bucket_rep(bk);
-        for (int i = 0; i < kTuneProblems; ++i) {
+        const int64_t count = tune_count(m, n, grid);
+        const int64_t a_sz = round_up(m * k, 64), b_sz = round_up(k * n, 64);
+        const int64_t c_sz = round_up(m * n, 64);
+        probs.assign((size_t)count, mg_problem{});
+        int64_t oa = 0, ob = 0;
+        for (int64_t i = 0; i < count; ++i) {
+          if (oa + a_sz > kTuneOperandElems) oa = 0;
+          if (ob + b_sz > kTuneOperandElems) ob = 0;
           mg_problem &q = probs[(size_t)i];
           q.m = m;
           q.n = n;
           q.k = k;
           q.alpha = 1.0;
           q.beta = 1.0;
-          q.A = dA;
+          q.A = static_cast<char *>(dA) + (size_t)oa * esz;
           q.lda = k;
-          q.B = dB;
+          q.B = static_cast<char *>(dB) + (size_t)ob * esz;
           q.ldb = n;
-          q.C = static_cast<char *>(dC) + (size_t)i * mat;
+          q.C = static_cast<char *>(dC) + (size_t)(i * c_sz) * esz;
           q.ldc = n;
+          oa += a_sz;
+          ob += b_sz;
         }
         float best = 0;
         int best_cls = heuristic_class(m, n);
@@ -437,7 +784,7 @@ int autotune(int dtype, int reps, hipStream_t s, mg_tune_table *out) {
           forced.dtype = dtype;
           for (int b = 0; b < MG_TUNE_BUCKETS; ++b) forced.cls[b] = c;
           Plan *p = nullptr;
-          rc = plan_create(dtype, kTuneProblems, probs.data(), &forced, &p);
+          rc = plan_create(dtype, count, probs.data(), &forced, &p);
           if (rc != MG_OK) break;
           float ms = 0;
           rc = time_plan(p, reps, s, e0, e1, &ms);

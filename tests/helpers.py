@@ -8,6 +8,10 @@ import numpy as np
 
 import synth
 
+# Native work divisions the library exports (mg_num_tile_cfgs); every one is
+# covered by the GPU parity tests.
+NATIVE_CFGS = 14
+
 U64 = 2.0 ** -53  # unit roundoff of FP64
 U32 = 2.0 ** -24
 

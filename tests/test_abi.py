@@ -9,6 +9,7 @@ import re
 import pytest
 
 import paper_1602_08477_amd as mg
+from helpers import NATIVE_CFGS
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
@@ -40,7 +41,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_version_and_cfgs():
     assert mg.lib().mg_version() >= 10000
-    assert mg.num_tile_cfgs() == 10  # the GPU parity tests cover every one of them
+    assert mg.num_tile_cfgs() == NATIVE_CFGS  # the GPU parity tests cover every one of them
     for c in range(mg.num_tile_cfgs()):
         info = mg.tile_cfg_info(c)
         assert info["bm"] % 32 == 0 and info["bn"] % 32 == 0 and info["threads"] in (256, 512)

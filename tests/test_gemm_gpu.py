@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import elementwise_bound, host_mats, log, to_dev, U32
+from helpers import NATIVE_CFGS, elementwise_bound, host_mats, log, to_dev, U32
 
 pytestmark = pytest.mark.gpu
 
@@ -42,7 +42,7 @@ def check_f64(got, A, B, C, alpha, beta, tag):
     assert worst <= 1.0, (tag, worst)
 
 
-@pytest.mark.parametrize("cfg", range(10))
+@pytest.mark.parametrize("cfg", range(NATIVE_CFGS))
 @pytest.mark.parametrize("shape", SHAPES)
 def test_native_f64_parity_all_cfgs(cfg, shape):
     m, n, k = shape
@@ -60,7 +60,7 @@ def test_native_f64_config1_n512():
     check_f64(got, A, B, C, 1.5, 0.5, "config1 n=512")
 
 
-@pytest.mark.parametrize("cfg", range(10))
+@pytest.mark.parametrize("cfg", range(NATIVE_CFGS))
 def test_small_integers_bit_exact(cfg):
     m, n, k = 150, 97, 301
     A = synth.small_int_matrix(31, 0, m, k)
@@ -166,7 +166,7 @@ def test_deterministic_repeats():
     assert all(torch.equal(outs[0], o) for o in outs[1:])
 
 
-@pytest.mark.parametrize("cfg", [0, 2, 4, 5, 7, 9])
+@pytest.mark.parametrize("cfg", [0, 2, 4, 5, 7, 9, 10, 12, 13])
 @pytest.mark.parametrize("shape", [(33, 17, 65), (129, 130, 131), (256, 256, 256), (300, 200, 517)])
 def test_native_f32_parity(cfg, shape):
     m, n, k = shape

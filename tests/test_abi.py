@@ -44,7 +44,7 @@ def test_version_and_cfgs():
     assert mg.num_tile_cfgs() == NATIVE_CFGS  # the GPU parity tests cover every one of them
     for c in range(mg.num_tile_cfgs()):
         info = mg.tile_cfg_info(c)
-        assert info["bm"] % 32 == 0 and info["bn"] % 32 == 0 and info["threads"] in (256, 512)
+        assert info["bm"] % 32 == 0 and info["bn"] % 32 == 0 and info["threads"] in (256, 512, 1024)
         assert mg.tile_cfg_info(c, mg.F32)["bk"] == 2 * info["bk"]
     with pytest.raises(mg.MgError):
         mg.tile_cfg_info(99)

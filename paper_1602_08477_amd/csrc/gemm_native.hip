@@ -143,13 +143,14 @@ int tile_cfg_info(int dtype, int cfg, int *bm, int *bn, int *bk, int *threads) {
 int pick_tile_cfg(int dtype, int64_t m, int64_t n, int64_t k) {
   (void)dtype;
   (void)k;
-  // Measured on MI355X (FP64, square n): 128x128 tiles on 8 wavefronts are
-  // fastest once there are two tiles per CU (n >= 4096: 84 % of peak at
-  // 8192), 128x64 on 8 wavefronts at one 128x128 tile per CU (n = 2048),
+  // Measured on MI355X (FP64 and FP32): 256x128 tiles on 16 wavefronts once
+  // every CU gets one (n >= 4096: 84 % of FP64 peak at 8192), 128x128 tiles
+  // with a 32-deep k-step at one per CU (n = 2048), 128x64 on 8 wavefronts,
   // then the small 4-wavefront tiles while they still give every CU work.
   auto tiles = [&](int c) { return ceil_div(m, kCfgs[c].bm) * ceil_div(n, kCfgs[c].bn); };
   const int64_t cus = 256;
-  if (tiles(5) >= 2 * cus) return 5;
+  if (tiles(12) >= cus) return 12;
+  if (tiles(13) >= cus) return 13;
   if (tiles(8) >= 2 * cus) return 8;
   if (tiles(2) >= 2 * cus) return 2;
   if (tiles(3) >= 2 * cus) return 3;

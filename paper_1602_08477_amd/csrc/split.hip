@@ -259,6 +259,9 @@ template <typename M, int FMW, int FNW, int THREADS>
 __device__ __forceinline__ void fold_partials(typename M::acc_t (&acc)[FMW][FNW],
                                               i4v (&dacc)[FMW][FNW], double *plane, double sc,
                                               bool first) {
+  // Opaque copy of the base: keeps the compiler from hoisting all FMW*FNW*4
+  // element addresses out of the k loop (64-bit each, they would not fit).
+  asm volatile("" : "+v"(plane));
 #pragma unroll
   for (int i = 0; i < FMW; ++i) {
 #pragma unroll
@@ -284,6 +287,7 @@ __device__ __forceinline__ void finish_tile(const SplitArgs &a, typename M::acc_
                                             i4v (&dacc)[FMW][FNW], const double *plane,
                                             bool only, int row0, int col0) {
   const double sc = ldexp(1.0, -a.bits * (a.s + 1));
+  asm volatile("" : "+v"(plane));
 #pragma unroll
   for (int i = 0; i < FMW; ++i) {
 #pragma unroll
@@ -752,7 +756,7 @@ int split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, const d
   return MG_OK;
 }
 
-int split_num_cfgs() { return 9; }
+int split_num_cfgs() { return 12; }
 
 // Product-kernel work division (measured on MI355X at n = 4096): the 256x256
 // direct-to-LDS tile once every CU gets one, then the 128x256 one, else the
@@ -812,6 +816,9 @@ int split_multiply(int algo, int slices, int64_t m, int64_t n, int64_t k, double
     case 6: return launch_split_dma<2, 4, 8, 4, 4, 64>(algo, a, L, s);  // 256x256, 8 waves, 4 x 64 B
     case 7: return launch_split_dma<4, 4, 4, 4, 4, 64>(algo, a, L, s);  // 256x256, 16 waves, 4 x 64 B
     case 8: return launch_split_dma<2, 4, 4, 4, 6, 64>(algo, a, L, s);  // 128x256, 8 waves, 6 x 64 B
+    case 9: return launch_split_dma<2, 4, 8, 4, 4, 64>(algo, a, L, s);  // 256x256, 8 waves, 4 x 64 B
+    case 10: return launch_split_dma<4, 2, 4, 8, 4, 64>(algo, a, L, s);  // 256x256, 8 waves, 4 x 64 B
+    case 11: return launch_split_dma<2, 4, 8, 4, 2, 128>(algo, a, L, s);  // 256x256, 8 waves, 2 x 128 B
   }
   set_error("unknown split cfg %d", cfg);
   return MG_ERR_INVALID_ARG;

@@ -11,6 +11,8 @@ import synth
 # Native work divisions the library exports (mg_num_tile_cfgs); every one is
 # covered by the GPU parity tests.
 NATIVE_CFGS = 14
+# Split product-kernel work divisions (mg_split_num_cfgs), all covered likewise.
+SPLIT_CFGS = 12
 
 U64 = 2.0 ** -53  # unit roundoff of FP64
 U32 = 2.0 ** -24

@@ -9,7 +9,7 @@ import re
 import pytest
 
 import paper_1602_08477_amd as mg
-from helpers import NATIVE_CFGS
+from helpers import NATIVE_CFGS, SPLIT_CFGS
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
@@ -48,8 +48,8 @@ def test_version_and_cfgs():
         assert mg.tile_cfg_info(c, mg.F32)["bk"] == 2 * info["bk"]
     with pytest.raises(mg.MgError):
         mg.tile_cfg_info(99)
-    assert mg.pick_tile_cfg(8192, 8192, 8192) == 5
-    assert mg.pick_tile_cfg(2048, 2048, 2048) == 8
+    assert mg.pick_tile_cfg(8192, 8192, 8192) == 12
+    assert mg.pick_tile_cfg(2048, 2048, 2048) == 13
     assert 0 <= mg.pick_tile_cfg(16, 16, 16) < mg.num_tile_cfgs()
 
 
@@ -104,7 +104,7 @@ def test_split_layout_and_errors():
     assert L["total_bytes"] >= L["p_off"] + 8 * 256 * 512
     Lb = mg.split_layout(mg.SPLIT_BF16, 6, 1, 1, 1)
     assert (Lb["mp"], Lb["np"], Lb["kp"], Lb["elem_bytes"]) == (256, 256, 128, 2)
-    assert mg.split_num_cfgs() == 9
+    assert mg.split_num_cfgs() == SPLIT_CFGS
     assert mg.split_default_slices(mg.SPLIT_I8) == 7
     assert mg.split_default_slices(mg.SPLIT_BF16) == 6
     with pytest.raises(mg.MgError):

@@ -15,7 +15,7 @@ import pytest
 import oracle
 import synth
 from oracle import split as osplit
-from helpers import host_mats, log, to_dev
+from helpers import SPLIT_CFGS, host_mats, log, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -228,7 +228,7 @@ def test_workspace_below_operands_is_not_an_overlap():
 
 
 @pytest.mark.parametrize("kind", ["i8", "bf16"])
-@pytest.mark.parametrize("cfg", list(range(9)))
+@pytest.mark.parametrize("cfg", list(range(SPLIT_CFGS)))
 def test_split_work_divisions_bit_exact(kind, cfg):
     """Every work division of the product kernel gives the oracle's bits."""
     algo = ALGOS[kind]

@@ -169,7 +169,8 @@ def bench_sizes(steps, warmup):
     4096 and (8192, 1024, 4096) with alpha = beta = 1), default work division:
     median kernel time from HIP events, warm operands; for n <= 2048 also a
     cold time with the L2 and MALL flushed by a 512 MiB write before each
-    launch."""
+    launch.  For context only, the platform BLAS (torch.addmm) is timed the
+    same way on the same operands."""
     import torch
     import paper_1602_08477_amd as mg
     import synth
@@ -189,10 +190,16 @@ def bench_sizes(steps, warmup):
         per, _ = time_launches(fn, reps, warmup, stream)
         ms = float(np.median(per))
         flop = 2.0 * m * n * k
+        # context: the platform BLAS (torch.addmm) on the same operands
+        ref = torch.empty_like(dC)
+        per_v, _ = time_launches(lambda: torch.addmm(dC, dA, dB, beta=beta, alpha=alpha, out=ref),
+                                 reps, warmup, stream)
+        ms_v = float(np.median(per_v))
         rec = {"m": m, "n": n, "k": k, "alpha": alpha, "beta": beta,
                "tile_cfg": mg.pick_tile_cfg(m, n, k), "ms": round(ms, 5),
                "tflops": round(flop / ms / 1e9, 3),
-               "pct_peak": round(100 * flop / ms / 1e9 / FP64_PEAK, 2)}
+               "pct_peak": round(100 * flop / ms / 1e9 / FP64_PEAK, 2),
+               "context_torch_addmm_tflops": round(flop / ms_v / 1e9, 3)}
         if max(m, n, k) <= 2048:
             cold = []
             for _ in range(reps):
@@ -205,7 +212,7 @@ def bench_sizes(steps, warmup):
                 cold.append(s.elapsed_time(e))
             rec["ms_cold"] = round(float(np.median(cold)), 5)
         out.append(rec)
-        del dA, dB, dC
+        del dA, dB, dC, ref
     del flush
     torch.cuda.empty_cache()
     return out
@@ -400,6 +407,13 @@ def cpu_baseline(n, target_s=12.0):
         if dt >= target_s / 4 or rows >= n:
             break
         rows = min(n, rows * 2 if dt < target_s / 16 else rows * 4)
+    if rows < n and dt < target_s:  # the timed sample: about target_s of work
+        rows = min(n, max(rows, int(rows * target_s / dt)))
+        A = synth.uniform_pm1(seed, synth.STREAM_A, rows * n).reshape(rows, n)
+        C = synth.uniform_pm1(seed, synth.STREAM_C, rows * n).reshape(rows, n)
+        t0 = time.perf_counter()
+        oracle.dgemm(1.0, A, B, 1.0, C)
+        dt = time.perf_counter() - t0
     tflops = 2.0 * rows * n * n / dt / 1e12
     cores = oracle.threads()
     # The whole small workloads, on all cores and on one core.

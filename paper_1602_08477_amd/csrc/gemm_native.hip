@@ -10,10 +10,8 @@ namespace {
 
 constexpr int kGroupM = 8;  // tile-rows walked together by the raster
 
-// MINW: minimum wavefronts per SIMD the register allocation must allow (the
-// second __launch_bounds__ argument); 1 leaves it to the compiler.
-template <typename T, int BM, int BN, bool VEC_OK, int WGM, int WGN, int BKM, int MINW>
-__global__ __launch_bounds__((TileShape<T, BM, BN, WGM, WGN, BKM>::THREADS), MINW) void gemm_native_kernel(
+template <typename T, int BM, int BN, bool VEC_OK, int WGM, int WGN, int BKM>
+__global__ __launch_bounds__((TileShape<T, BM, BN, WGM, WGN, BKM>::THREADS)) void gemm_native_kernel(
     GemmArgs<T> g, int tiles_m, int tiles_n) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T *smem = reinterpret_cast<T *>(lds_raw);
@@ -43,12 +41,10 @@ constexpr CfgDesc kCfgs[] = {{128, 128, 2, 2, 1}, {128, 64, 2, 2, 1}, {64, 64, 2
                              {64, 32, 2, 2, 1},   {32, 32, 2, 2, 1},  {128, 128, 4, 2, 1},
                              {128, 128, 2, 4, 1}, {64, 64, 2, 2, 2},  {128, 64, 4, 2, 1},
                              {128, 64, 2, 2, 2},  {256, 128, 4, 2, 1}, {128, 256, 2, 4, 1},
-                             {256, 128, 4, 4, 1}, {128, 128, 4, 2, 2},  {128, 128, 2, 2, 1},
-                             {128, 64, 2, 2, 1}};
+                             {256, 128, 4, 4, 1}, {128, 128, 4, 2, 2}};
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
-template <typename T, int BM, int BN, bool VEC_OK, int WGM = 2, int WGN = 2, int BKM = 1,
-          int MINW = 1>
+template <typename T, int BM, int BN, bool VEC_OK, int WGM = 2, int WGN = 2, int BKM = 1>
 int launch_one(const GemmArgs<T> &g, hipStream_t s) {
   typedef TileShape<T, BM, BN, WGM, WGN, BKM> S;
   const int tiles_m = (g.m + BM - 1) / BM, tiles_n = (g.n + BN - 1) / BN;
@@ -57,7 +53,7 @@ int launch_one(const GemmArgs<T> &g, hipStream_t s) {
     set_error("too many tiles (%lld)", (long long)tiles);
     return MG_ERR_INVALID_ARG;
   }
-  auto kern = gemm_native_kernel<T, BM, BN, VEC_OK, WGM, WGN, BKM, MINW>;
+  auto kern = gemm_native_kernel<T, BM, BN, VEC_OK, WGM, WGN, BKM>;
   static bool attr_set = false;  // per template instance
   if (!attr_set) {
     MG_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -88,8 +84,6 @@ int launch_cfg(int cfg, const GemmArgs<T> &g, hipStream_t s) {
     case 11: return launch_one<T, 128, 256, VEC_OK, 2, 4, 1>(g, s);
     case 12: return launch_one<T, 256, 128, VEC_OK, 4, 4, 1>(g, s);
     case 13: return launch_one<T, 128, 128, VEC_OK, 4, 2, 2>(g, s);
-    case 14: return launch_one<T, 128, 128, VEC_OK, 2, 2, 1, 2>(g, s);  // 2 workgroups per CU
-    case 15: return launch_one<T, 128, 64, VEC_OK, 2, 2, 1, 3>(g, s);   // 3 workgroups per CU
   }
   set_error("unknown tile cfg %d", cfg);
   return MG_ERR_INVALID_ARG;

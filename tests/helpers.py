@@ -10,7 +10,7 @@ import synth
 
 # Native work divisions the library exports (mg_num_tile_cfgs); every one is
 # covered by the GPU parity tests.
-NATIVE_CFGS = 16
+NATIVE_CFGS = 14
 # Split product-kernel work divisions (mg_split_num_cfgs), all covered likewise.
 SPLIT_CFGS = 12
 

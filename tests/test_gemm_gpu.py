@@ -166,7 +166,7 @@ def test_deterministic_repeats():
     assert all(torch.equal(outs[0], o) for o in outs[1:])
 
 
-@pytest.mark.parametrize("cfg", [0, 2, 4, 5, 7, 9, 10, 12, 13, 14, 15])
+@pytest.mark.parametrize("cfg", [0, 2, 4, 5, 7, 9, 10, 12, 13])
 @pytest.mark.parametrize("shape", [(33, 17, 65), (129, 130, 131), (256, 256, 256), (300, 200, 517)])
 def test_native_f32_parity(cfg, shape):
     m, n, k = shape

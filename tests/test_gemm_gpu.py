@@ -206,3 +206,29 @@ def test_config2_sizes_sampled(mnk):
     got = dC[rt][:, ct].cpu().numpy()
     check_f64(got, As, Bs, Cs, 1.0, 1.0, f"config2 {mnk} sampled")
     assert torch.isfinite(dC).all()
+
+
+def test_metamorphic_transpose_bit_exact():
+    """(A B)^T = B^T A^T: every output sums the same products in the same k
+    order whichever operand feeds which side of the matrix core, so the two
+    results agree bit for bit."""
+    m, n, k = 300, 200, 517
+    A, B, _ = host_mats(41, m, n, k)
+    C1 = run(A, B, np.zeros((m, n)), 1.0, 0.0).cpu().numpy()
+    C2 = run(np.ascontiguousarray(B.T), np.ascontiguousarray(A.T), np.zeros((n, m)), 1.0,
+             0.0).cpu().numpy()
+    assert np.array_equal(C1, C2.T)
+
+
+def test_metamorphic_row_permutation_and_power_of_two_scaling():
+    """Permuting the rows of A permutes the rows of C, and scaling A by 2^t
+    scales C by 2^t, both bit for bit (each output's arithmetic depends only
+    on its own row of A and column of B)."""
+    m, n, k = 257, 190, 333
+    A, B, _ = host_mats(42, m, n, k)
+    perm = np.argsort(synth.uniform_unit(42, 9, m))
+    base = run(A, B, np.zeros((m, n)), 1.0, 0.0).cpu().numpy()
+    permuted = run(np.ascontiguousarray(A[perm]), B, np.zeros((m, n)), 1.0, 0.0).cpu().numpy()
+    assert np.array_equal(permuted, base[perm])
+    scaled = run(A * 2.0 ** 37, B, np.zeros((m, n)), 1.0, 0.0).cpu().numpy()
+    assert np.array_equal(scaled, base * 2.0 ** 37)

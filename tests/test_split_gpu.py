@@ -239,3 +239,26 @@ def test_split_work_divisions_bit_exact(kind, cfg):
     mg.gemm_split(to_dev(A), to_dev(B), dC, 1.5, -0.5, algo=algo, slices=s, cfg=cfg)
     torch.cuda.synchronize()
     assert np.array_equal(dC.cpu().numpy(), osplit.split_gemm(1.5, A, B, -0.5, C, s, kind))
+
+
+@pytest.mark.parametrize("kind", ["i8", "bf16"])
+def test_split_row_permutation_and_power_of_two_scaling(kind):
+    """A row's exponent, slices and products depend only on that row, so
+    permuting the rows of A permutes the rows of C and scaling a row of A by
+    2^t scales the same row of C (beta = 0), bit for bit."""
+    m, n, k = 200, 150, 300
+    algo = ALGOS[kind]
+    s = mg.split_default_slices(algo)
+    A, B, _ = spread(61, m, n, k)
+
+    def go(Ax):
+        dC = torch.zeros(m, n, dtype=torch.float64, device="cuda")
+        mg.gemm_split(to_dev(Ax), to_dev(B), dC, 1.0, 0.0, algo=algo, slices=s)
+        torch.cuda.synchronize()
+        return dC.cpu().numpy()
+
+    base = go(A)
+    perm = np.argsort(synth.uniform_unit(61, 9, m))
+    assert np.array_equal(go(np.ascontiguousarray(A[perm])), base[perm])
+    t = np.arange(m) % 7 - 3  # per-row power-of-two scale factors
+    assert np.array_equal(go(A * np.ldexp(1.0, t)[:, None]), base * np.ldexp(1.0, t)[:, None])

@@ -41,6 +41,7 @@ BF16_PEAK = 2500.0  # TFLOP/s dense
 METRIC = "GEMM TFLOP/s & %peak: FP64 vs split-prec at 1e-12 rel err; p99 latency"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dgemm_f64_n8192.json")
 KERNEL_SOURCES = ["paper_1602_08477_amd/csrc/gemm_tile.h",
+                  "paper_1602_08477_amd/csrc/gemm_dma.h",
                   "paper_1602_08477_amd/csrc/gemm_native.hip",
                   "paper_1602_08477_amd/csrc/common.h"]
 

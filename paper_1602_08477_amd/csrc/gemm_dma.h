@@ -1,0 +1,230 @@
+// Native GEMM tile fed by direct global->LDS loads (gfx950
+// global_load_lds_dwordx4) into an NS-stage LDS ring.
+//
+// Same hierarchy as gemm_tile (Section 4.2.2 tiling: block = macro-tile of
+// C, threads stage A/B tiles in shared memory, each lane accumulates MFMA
+// fragments), but the loads of k-steps t+1 .. t+NS-1 are in flight while the
+// matrix cores work on step t, and no registers or LDS write instructions are
+// spent on staging: each lane's 16 bytes land at the wave's LDS base + 16*lane.
+// Requires 16-byte aligned operands (base aligned, pitch a multiple of the
+// 16-byte element count); ragged edges are read from clamped in-bounds
+// chunks and never stored, and k past the problem's k is zeroed in LDS on
+// both operands before the last step's multiply (the same sums as the
+// zero-filled tail of the register-staged tile).
+//
+// One k-step covers 128 bytes of k (16 FP64 / 32 FP32 values).  LDS stage:
+//   A [BM rows][128 B], 16-byte chunk c of row r stored at chunk c ^ ((r>>1)&7)
+//     so the fragment reads of 16 consecutive rows hit distinct banks;
+//   B [128/size rows of k][BN*size B], row-major like B in HBM, chunks XOR-
+//     swizzled per k row so the four lane groups' rows of one fragment read
+//     fall on different banks.
+#pragma once
+
+#include "gemm_tile.h"
+
+namespace mg {
+
+template <typename T, int BM, int BN, int WGM, int WGN, int NS>
+struct DmaShape {
+  static constexpr int THREADS = 64 * WGM * WGN;
+  static constexpr int WAVES = WGM * WGN;
+  static constexpr int ESZ = sizeof(T);
+  static constexpr int VEC = 16 / ESZ;
+  static constexpr int BK = 128 / ESZ;
+  static constexpr int RB = BN * ESZ;          // B row bytes in LDS
+  static constexpr int CPB = RB / 16;          // 16-byte chunks per B row
+  static constexpr int A_BYTES = BM * 128;
+  static constexpr int STAGE = A_BYTES + 128 * BN;  // B block: BK rows of RB bytes
+  static constexpr size_t LDS_BYTES = (size_t)NS * STAGE;
+  static constexpr int IA = BM / 8 / WAVES;    // 1 KB DMA instructions per wave, A
+  static constexpr int IB = BN / 8 / WAVES;    // and B
+  static constexpr int WM = BM / WGM, WN = BN / WGN;
+  static constexpr int FM = WM / 16, FN = WN / 16;
+  static_assert(IA >= 1 && IA * 8 * WAVES == BM, "whole A instructions per wave");
+  static_assert(IB >= 1 && IB * 8 * WAVES == BN, "whole B instructions per wave");
+  static_assert(FM >= 1 && FN >= 1 && WM % 16 == 0 && WN % 16 == 0, "16x16 blocks per wave");
+  static_assert(CPB >= 8 && (CPB & (CPB - 1)) == 0, "B rows of 2^j >= 8 chunks");
+  static_assert(NS >= 2 && LDS_BYTES <= 160 * 1024, "ring fits in LDS");
+};
+
+__device__ __forceinline__ int dma_swz_a(int row, int c) { return c ^ ((row >> 1) & 7); }
+
+// FP64 fragments read 8-byte values of 16 consecutive columns (128 B) from the
+// rows 2(4r+g)+v of the four lane groups g: flip the 128-byte half by a bit
+// that differs between any two of them.  FP32 reads 64 B from rows 4(4r+g)+v:
+// rotate by 64-byte quarters with (row/4) mod 4.
+template <typename T, int CPB>
+__device__ __forceinline__ int dma_swz_b(int row, int c) {
+  if (sizeof(T) == 8) return c ^ ((((row >> 1) ^ (row >> 2)) & 1) << 3);
+  return c ^ ((((row >> 2) & 3) << 2) & (CPB - 1));
+}
+
+__device__ __forceinline__ void dma_lds16(const void *src, unsigned char *lds_dst) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds_dst, 16, 0,
+                                   0);
+}
+
+template <int N>
+__device__ __forceinline__ void dma_wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  // gfx9 s_waitcnt encoding: vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt[15:14]
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// Waits until at most q k-steps' DMAs (DPS instructions each) are pending.
+template <int DPS, int NS>
+__device__ __forceinline__ void dma_wait_steps(int q) {
+  if (q <= 0) dma_wait_vmcnt<0>();
+  else if (q == 1 || NS <= 2) dma_wait_vmcnt<DPS>();
+  else if (q == 2 || NS <= 3) dma_wait_vmcnt<2 * DPS>();
+  else dma_wait_vmcnt<3 * DPS>();
+}
+
+template <typename T, int BM, int BN, int WGM, int WGN, int NS>
+__device__ __forceinline__ void gemm_dma_tile(const GemmArgs<T> &g, int m0, int n0,
+                                              unsigned char *lds) {
+  typedef DmaShape<T, BM, BN, WGM, WGN, NS> S;
+  typedef Mfma<T> M;
+  typedef typename M::vec_t V;
+  typedef typename M::acc_t Acc;
+  constexpr int ESZ = S::ESZ, VEC = S::VEC, BK = S::BK;
+  constexpr int DPS = S::IA + S::IB;  // DMA instructions per k-step per wave
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm0 = (wave / WGN) * S::WM, wn0 = (wave % WGN) * S::WN;
+  const int gq = lane >> 4, l16 = lane & 15;
+
+  // Source of this lane's chunk in every DMA slot, without the k-step offset.
+  // A slot u: rows 8q .. 8q+7 (q = wave*IA + u), lane -> row 8q + lane/8,
+  // physical chunk lane%8 holding logical chunk c.  B slot u: LDS bytes
+  // [1024q, 1024q + 1024) of the B block.  Rows past m and chunks past n are
+  // clamped to the last valid ones.
+  const char *A = reinterpret_cast<const char *>(g.A);
+  const char *B = reinterpret_cast<const char *>(g.B);
+  const int last_col_chunk = ((g.n - 1) / VEC) * VEC;
+  const char *asrc[S::IA];
+  int akofs[S::IA];
+#pragma unroll
+  for (int u = 0; u < S::IA; ++u) {
+    const int row = 8 * (wave * S::IA + u) + (lane >> 3);
+    akofs[u] = dma_swz_a(row, lane & 7) * VEC;
+    const int gr = min(m0 + row, g.m - 1);
+    asrc[u] = A + ((int64_t)gr * g.lda + akofs[u]) * ESZ;
+  }
+  const char *bsrc[S::IB];
+  int bkrow[S::IB];
+#pragma unroll
+  for (int u = 0; u < S::IB; ++u) {
+    const int o = (wave * S::IB + u) * 1024 + lane * 16;
+    const int row = o / S::RB;
+    const int c = dma_swz_b<T, S::CPB>(row, (o % S::RB) >> 4);
+    bkrow[u] = row;
+    const int gc = min(n0 + c * VEC, last_col_chunk);
+    bsrc[u] = B + ((int64_t)row * g.ldb + gc) * ESZ;
+  }
+
+  const int KT = (g.k + BK - 1) / BK;
+  const int last_k_chunk = ((g.k - 1) / VEC) * VEC;
+  auto issue = [&](int kt) {
+    const int kbase = kt * BK;
+    unsigned char *la = lds + (kt % NS) * S::STAGE;
+    unsigned char *lb = la + S::A_BYTES;
+    if (kbase + BK <= g.k) {
+#pragma unroll
+      for (int u = 0; u < S::IA; ++u)
+        dma_lds16(asrc[u] + (int64_t)kbase * ESZ, la + (wave * S::IA + u) * 1024);
+      const int64_t bstep = (int64_t)kbase * g.ldb * ESZ;
+#pragma unroll
+      for (int u = 0; u < S::IB; ++u) dma_lds16(bsrc[u] + bstep, lb + (wave * S::IB + u) * 1024);
+    } else {  // partial last step: clamp k to the last valid chunk / row
+#pragma unroll
+      for (int u = 0; u < S::IA; ++u) {
+        const int kk = min(kbase + akofs[u], last_k_chunk);
+        dma_lds16(asrc[u] + (int64_t)(kk - akofs[u]) * ESZ, la + (wave * S::IA + u) * 1024);
+      }
+#pragma unroll
+      for (int u = 0; u < S::IB; ++u) {
+        const int kr = min(kbase + bkrow[u], g.k - 1);
+        dma_lds16(bsrc[u] + (int64_t)(kr - bkrow[u]) * g.ldb * ESZ,
+                  lb + (wave * S::IB + u) * 1024);
+      }
+    }
+  };
+
+  Acc acc[S::FM][S::FN];
+#pragma unroll
+  for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < S::FN; ++j) acc[i][j] = Acc{};
+
+  auto compute = [&](const unsigned char *As, const unsigned char *Bs) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int kc = 4 * r + gq;  // this lane group's 16-byte k chunk
+      V a[S::FM];
+#pragma unroll
+      for (int i = 0; i < S::FM; ++i) {
+        const int row = wm0 + 16 * i + l16;
+        a[i] = *reinterpret_cast<const V *>(As + row * 128 + dma_swz_a(row, kc) * 16);
+      }
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const int kr = kc * VEC + v;
+        T b[S::FN];
+#pragma unroll
+        for (int j = 0; j < S::FN; ++j) {
+          const int byte = (wn0 + 16 * j + l16) * ESZ;
+          b[j] = *reinterpret_cast<const T *>(Bs + kr * S::RB +
+                                              dma_swz_b<T, S::CPB>(kr, byte >> 4) * 16 +
+                                              (byte & 15));
+        }
+#pragma unroll
+        for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+          for (int j = 0; j < S::FN; ++j) acc[i][j] = M::mma(a[i][v], b[j], acc[i][j]);
+      }
+    }
+  };
+
+  // Last, partial k-step: zero every k >= kvalid of the landed stage (A
+  // columns, B rows), so values read from clamped addresses never reach the
+  // sums; the same zeros the register-staged tile loads past k.
+  auto zero_tail = [&](unsigned char *As, unsigned char *Bs, int kvalid) {
+    for (int e = tid; e < BM * 8; e += S::THREADS) {
+      const int row = e >> 3, c = e & 7;
+      if ((c + 1) * VEC <= kvalid) continue;
+      T *p = reinterpret_cast<T *>(As + row * 128 + dma_swz_a(row, c) * 16);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v)
+        if (c * VEC + v >= kvalid) p[v] = T(0);
+    }
+    for (int e = tid; e < BK * S::CPB; e += S::THREADS) {
+      const int kr = e / S::CPB;
+      if (kr >= kvalid) *reinterpret_cast<V *>(Bs + e * 16) = V{};
+    }
+  };
+
+#pragma unroll
+  for (int q = 0; q < NS - 1; ++q)
+    if (q < KT) issue(q);
+  for (int kt = 0; kt < KT; ++kt) {
+    // step kt has landed once only the later issued steps may be pending
+    dma_wait_steps<DPS, NS>(min(KT - 1, kt + NS - 2) - kt);
+    __builtin_amdgcn_s_barrier();
+    if (kt + NS - 1 < KT) issue(kt + NS - 1);
+    unsigned char *As = lds + (kt % NS) * S::STAGE;
+    unsigned char *Bs = As + S::A_BYTES;
+    const int kvalid = g.k - kt * BK;
+    if (kvalid < BK) {  // only the last step; nothing is in flight any more
+      zero_tail(As, Bs, kvalid);
+      __syncthreads();
+    }
+    compute(As, Bs);
+  }
+
+  Epilogue<T, true>::template store<S::FM, S::FN>(g, acc, m0 + wm0, n0 + wn0, lane);
+}
+
+}  // namespace mg

@@ -2,6 +2,7 @@
 // tiling), work division chosen per shape on the host.
 #include "gemm_native.h"
 
+#include "gemm_dma.h"
 #include "gemm_tile.h"
 
 namespace mg {
@@ -21,6 +22,16 @@ __global__ __launch_bounds__((TileShape<T, BM, BN, WGM, WGN, BKM>::THREADS)) voi
   gemm_tile<T, BM, BN, VEC_OK, WGM, WGN, BKM>(g, tm * BM, tn * BN, smem);
 }
 
+template <typename T, int BM, int BN, int WGM, int WGN, int NS>
+__global__ __launch_bounds__((DmaShape<T, BM, BN, WGM, WGN, NS>::THREADS)) void gemm_dma_kernel(
+    GemmArgs<T> g, int tiles_m, int tiles_n) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  int tm, tn;
+  const int t = xcd_remap(blockIdx.x, tiles_m * tiles_n);
+  grouped_tile(t, tiles_m, tiles_n, kGroupM, tm, tn);
+  gemm_dma_tile<T, BM, BN, WGM, WGN, NS>(g, tm * BM, tn * BN, lds);
+}
+
 // C <- beta*C (alpha == 0 or k == 0).  beta == 0 writes zeros without reading.
 template <typename T>
 __global__ void scale_kernel(T *C, int64_t ldc, int m, int n, T beta) {
@@ -36,12 +47,17 @@ __global__ void scale_kernel(T *C, int64_t ldc, int m, int n, T beta) {
 struct CfgDesc {
   int bm, bn, wgm, wgn, bkm;
 };
+// Work divisions 0-13 stage A and B through registers; 14-18 load them
+// straight into an LDS ring (16-byte aligned operands only: otherwise a
+// register-staged division of the same macro-tile runs).
 // Work divisions: macro-tile, wavefront grid, k-step multiplier.
 constexpr CfgDesc kCfgs[] = {{128, 128, 2, 2, 1}, {128, 64, 2, 2, 1}, {64, 64, 2, 2, 1},
                              {64, 32, 2, 2, 1},   {32, 32, 2, 2, 1},  {128, 128, 4, 2, 1},
                              {128, 128, 2, 4, 1}, {64, 64, 2, 2, 2},  {128, 64, 4, 2, 1},
                              {128, 64, 2, 2, 2},  {256, 128, 4, 2, 1}, {128, 256, 2, 4, 1},
-                             {256, 128, 4, 4, 1}, {128, 128, 4, 2, 2}};
+                             {256, 128, 4, 4, 1}, {128, 128, 4, 2, 2},  {64, 64, 2, 2, 1},
+                             {64, 32, 2, 2, 1},   {128, 64, 2, 2, 1},  {128, 128, 2, 4, 1},
+                             {256, 128, 4, 4, 1}};
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
 template <typename T, int BM, int BN, bool VEC_OK, int WGM = 2, int WGN = 2, int BKM = 1>
@@ -54,6 +70,29 @@ int launch_one(const GemmArgs<T> &g, hipStream_t s) {
     return MG_ERR_INVALID_ARG;
   }
   auto kern = gemm_native_kernel<T, BM, BN, VEC_OK, WGM, WGN, BKM>;
+  static bool attr_set = false;  // per template instance
+  if (!attr_set) {
+    MG_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)S::LDS_BYTES));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(S::THREADS), S::LDS_BYTES, s, g, tiles_m,
+                     tiles_n);
+  MG_HIP_TRY(hipGetLastError());
+  return MG_OK;
+}
+
+template <typename T, int BM, int BN, int WGM, int WGN, int NS>
+int launch_dma(const GemmArgs<T> &g, hipStream_t s) {
+  typedef DmaShape<T, BM, BN, WGM, WGN, NS> S;
+  const int tiles_m = (g.m + BM - 1) / BM, tiles_n = (g.n + BN - 1) / BN;
+  const int64_t tiles = (int64_t)tiles_m * tiles_n;
+  if (tiles > INT32_MAX) {
+    set_error("too many tiles (%lld)", (long long)tiles);
+    return MG_ERR_INVALID_ARG;
+  }
+  auto kern = gemm_dma_kernel<T, BM, BN, WGM, WGN, NS>;
   static bool attr_set = false;  // per template instance
   if (!attr_set) {
     MG_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -84,6 +123,19 @@ int launch_cfg(int cfg, const GemmArgs<T> &g, hipStream_t s) {
     case 11: return launch_one<T, 128, 256, VEC_OK, 2, 4, 1>(g, s);
     case 12: return launch_one<T, 256, 128, VEC_OK, 4, 4, 1>(g, s);
     case 13: return launch_one<T, 128, 128, VEC_OK, 4, 2, 2>(g, s);
+    case 14:
+      return VEC_OK ? launch_dma<T, 64, 64, 2, 2, 4>(g, s) : launch_one<T, 64, 64, VEC_OK>(g, s);
+    case 15:
+      return VEC_OK ? launch_dma<T, 64, 32, 2, 2, 4>(g, s) : launch_one<T, 64, 32, VEC_OK>(g, s);
+    case 16:
+      return VEC_OK ? launch_dma<T, 128, 64, 2, 2, 4>(g, s)
+                    : launch_one<T, 128, 64, VEC_OK>(g, s);
+    case 17:
+      return VEC_OK ? launch_dma<T, 128, 128, 2, 4, 3>(g, s)
+                    : launch_one<T, 128, 128, VEC_OK, 4, 2, 2>(g, s);
+    case 18:
+      return VEC_OK ? launch_dma<T, 256, 128, 4, 4, 3>(g, s)
+                    : launch_one<T, 256, 128, VEC_OK, 4, 4, 1>(g, s);
   }
   set_error("unknown tile cfg %d", cfg);
   return MG_ERR_INVALID_ARG;
@@ -143,15 +195,17 @@ int tile_cfg_info(int dtype, int cfg, int *bm, int *bn, int *bk, int *threads) {
 int pick_tile_cfg(int dtype, int64_t m, int64_t n, int64_t k) {
   (void)dtype;
   (void)k;
-  // Measured on MI355X (FP64 and FP32): 256x128 tiles on 16 wavefronts once
-  // every CU gets one (n >= 4096: 84 % of FP64 peak at 8192), 128x128 tiles
-  // with a 32-deep k-step at one per CU (n = 2048), 128x64 on 8 wavefronts,
-  // then the small 4-wavefront tiles while they still give every CU work.
+  // Measured on MI355X (FP64 and FP32, 16-byte aligned operands): 256x128
+  // tiles on 16 wavefronts with a 3-stage direct-load ring once every CU gets
+  // one (n >= 4096: 87 % of FP64 peak at 8192), the 128x128 8-wavefront ring
+  // at one tile per CU (n = 2048), the 64x32 ring at two (n = 1024), then
+  // the small register-staged tiles while they still give every CU work.
+  // Unaligned operands run the register-staged division of the same tile.
   auto tiles = [&](int c) { return ceil_div(m, kCfgs[c].bm) * ceil_div(n, kCfgs[c].bn); };
   const int64_t cus = 256;
-  if (tiles(12) >= cus) return 12;
-  if (tiles(13) >= cus) return 13;
-  if (tiles(8) >= 2 * cus) return 8;
+  if (tiles(18) >= cus) return 18;
+  if (tiles(17) >= cus) return 17;
+  if (tiles(15) >= 2 * cus) return 15;
   if (tiles(2) >= 2 * cus) return 2;
   if (tiles(3) >= 2 * cus) return 3;
   return 4;

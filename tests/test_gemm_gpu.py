@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import NATIVE_CFGS, elementwise_bound, host_mats, log, to_dev, U32
+from helpers import DMA_CFGS, NATIVE_CFGS, elementwise_bound, host_mats, log, to_dev, U32
 
 pytestmark = pytest.mark.gpu
 
@@ -232,3 +232,52 @@ def test_metamorphic_row_permutation_and_power_of_two_scaling():
     assert np.array_equal(permuted, base[perm])
     scaled = run(A * 2.0 ** 37, B, np.zeros((m, n)), 1.0, 0.0).cpu().numpy()
     assert np.array_equal(scaled, base * 2.0 ** 37)
+
+
+def padded(cols):
+    """A row pitch that keeps 16-byte rows for FP64 and FP32 and leaves padding."""
+    return (cols + 7) // 8 * 8 + 8
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("cfg", DMA_CFGS)
+@pytest.mark.parametrize("shape", [(33, 17, 65), (70, 45, 15), (129, 130, 131), (300, 200, 517),
+                                   (256, 256, 256), (257, 129, 33)])
+def test_native_dma_aligned_ragged(dt, cfg, shape):
+    """Direct-to-LDS work divisions on 16-byte aligned operands with ragged m,
+    n and k: the padding of A and B holds NaN (read by edge chunks, never
+    allowed into a sum) and C's padding a canary that must survive."""
+    m, n, k = shape
+    A, B, C = host_mats(43 + m + n, m, n, k)
+    dtype = torch.float64 if dt == "f64" else torch.float32
+    if dt == "f32":
+        A, B, C = (x.astype(np.float32).astype(np.float64) for x in (A, B, C))
+    dA = to_dev(A, dtype, padded(k))
+    dB = to_dev(B, dtype, padded(n))
+    dC = to_dev(C, dtype, padded(n), fill=12345.0)
+    mg.gemm(dA, dB, dC, 1.5, 0.5, cfg=cfg)
+    torch.cuda.synchronize()
+    parent = dC.as_strided((m, padded(n)), (padded(n), 1)).cpu().numpy()
+    assert (parent[:, n:] == 12345.0).all()
+    got = dC.double().cpu().numpy()
+    if dt == "f64":
+        check_f64(got, A, B, C, 1.5, 0.5, f"dma cfg{cfg} {shape}")
+    else:
+        ref = oracle.dgemm(1.5, A, B, 0.5, C)
+        assert oracle.rel_fro_err(got, ref) <= 1e-5
+        assert (np.abs(got - ref) <= elementwise_bound(1.5, A, B, 0.5, C, k, u=U32)).all()
+
+
+@pytest.mark.parametrize("cfg", DMA_CFGS)
+def test_native_dma_matches_register_staged_bitwise(cfg):
+    """Both staging schemes run the same k order and epilogue: identical bits."""
+    m, n, k = 300, 260, 333
+    A, B, C = host_mats(44, m, n, k)
+    outs = []
+    for c in (cfg, 0):
+        dC = to_dev(C, torch.float64, padded(n))
+        mg.gemm(to_dev(A, torch.float64, padded(k)), to_dev(B, torch.float64, padded(n)), dC,
+                1.0, 1.0, cfg=c)
+        torch.cuda.synchronize()
+        outs.append(dC.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])

@@ -47,7 +47,7 @@ __global__ void scale_kernel(T *C, int64_t ldc, int m, int n, T beta) {
 struct CfgDesc {
   int bm, bn, wgm, wgn, bkm;
 };
-// Work divisions 0-13 stage A and B through registers; 14-18 load them
+// Work divisions 0-13 stage A and B through registers; 14-21 load them
 // straight into an LDS ring (16-byte aligned operands only: otherwise a
 // register-staged division of the same macro-tile runs).
 // Work divisions: macro-tile, wavefront grid, k-step multiplier.
@@ -57,7 +57,8 @@ constexpr CfgDesc kCfgs[] = {{128, 128, 2, 2, 1}, {128, 64, 2, 2, 1}, {64, 64, 2
                              {128, 64, 2, 2, 2},  {256, 128, 4, 2, 1}, {128, 256, 2, 4, 1},
                              {256, 128, 4, 4, 1}, {128, 128, 4, 2, 2},  {64, 64, 2, 2, 1},
                              {64, 32, 2, 2, 1},   {128, 64, 2, 2, 1},  {128, 128, 2, 4, 1},
-                             {256, 128, 4, 4, 1}};
+                             {256, 128, 4, 4, 1},  {32, 32, 2, 2, 1},   {64, 64, 4, 2, 1},
+                             {128, 128, 2, 4, 1}};
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
 template <typename T, int BM, int BN, bool VEC_OK, int WGM = 2, int WGN = 2, int BKM = 1>
@@ -136,6 +137,13 @@ int launch_cfg(int cfg, const GemmArgs<T> &g, hipStream_t s) {
     case 18:
       return VEC_OK ? launch_dma<T, 256, 128, 4, 4, 3>(g, s)
                     : launch_one<T, 256, 128, VEC_OK, 4, 4, 1>(g, s);
+    case 19:
+      return VEC_OK ? launch_dma<T, 32, 32, 2, 2, 4>(g, s) : launch_one<T, 32, 32, VEC_OK>(g, s);
+    case 20:
+      return VEC_OK ? launch_dma<T, 64, 64, 4, 2, 4>(g, s) : launch_one<T, 64, 64, VEC_OK>(g, s);
+    case 21:
+      return VEC_OK ? launch_dma<T, 128, 128, 2, 4, 2>(g, s)
+                    : launch_one<T, 128, 128, VEC_OK, 4, 2, 2>(g, s);
   }
   set_error("unknown tile cfg %d", cfg);
   return MG_ERR_INVALID_ARG;
@@ -195,17 +203,17 @@ int tile_cfg_info(int dtype, int cfg, int *bm, int *bn, int *bk, int *threads) {
 int pick_tile_cfg(int dtype, int64_t m, int64_t n, int64_t k) {
   (void)dtype;
   (void)k;
-  // Measured on MI355X (FP64 and FP32, 16-byte aligned operands): 256x128
-  // tiles on 16 wavefronts with a 3-stage direct-load ring once every CU gets
-  // one (n >= 4096: 87 % of FP64 peak at 8192), the 128x128 8-wavefront ring
-  // at one tile per CU (n = 2048), the 64x32 ring at two (n = 1024), then
-  // the small register-staged tiles while they still give every CU work.
-  // Unaligned operands run the register-staged division of the same tile.
+  // Measured on MI355X (FP64 and FP32, 16-byte aligned operands): 128x128
+  // tiles on 8 wavefronts with a 2-stage direct-load ring (two workgroups per
+  // CU) once every CU gets a tile (n >= 2048; 90 % of FP64 peak at 8192),
+  // the 64x32 ring at two tiles per CU (n = 1024), the 32x32 ring at one
+  // (n = 512), then the small register-staged tiles.  Unaligned operands run
+  // a register-staged division of the same macro-tile.
   auto tiles = [&](int c) { return ceil_div(m, kCfgs[c].bm) * ceil_div(n, kCfgs[c].bn); };
   const int64_t cus = 256;
-  if (tiles(18) >= cus) return 18;
-  if (tiles(17) >= cus) return 17;
+  if (tiles(21) >= cus) return 21;
   if (tiles(15) >= 2 * cus) return 15;
+  if (tiles(19) >= cus) return 19;
   if (tiles(2) >= 2 * cus) return 2;
   if (tiles(3) >= 2 * cus) return 3;
   return 4;

@@ -36,20 +36,6 @@ __device__ __forceinline__ int exp_of(double x) {
 }
 
 // ------------------------------------------------------------ step 1: scales
-__global__ void row_exp_kernel(const double *A, int64_t lda, int m, int k, int mp, int *E) {
-  const int row = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
-  const int lane = threadIdx.x & 63;
-  if (row >= mp) return;  // uniform per wave
-  int e = INT_MIN;
-  if (row < m) {
-    const double *p = A + (int64_t)row * lda;
-    for (int c = lane; c < k; c += 64) e = max(e, exp_of(p[c]));
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) e = max(e, __shfl_xor(e, off));
-  if (lane == 0) E[row] = (e == INT_MIN) ? 0 : e;
-}
-
 __global__ void fill_int_kernel(int *p, int count, int v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = v;
@@ -68,11 +54,6 @@ __global__ void col_exp_kernel(const double *B, int64_t ldb, int k, int n, int *
     for (int r = ch * kColRows; r < r1; ++r) e = max(e, exp_of(B[(int64_t)r * ldb + j]));
     if (e != INT_MIN) atomicMax(F + j, e);
   }
-}
-
-__global__ void col_exp_finish_kernel(int *F, int n, int np) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < np && (j >= n || F[j] == INT_MIN)) F[j] = 0;
 }
 
 // ------------------------------------------------------------ step 2: slices
@@ -119,39 +100,67 @@ __device__ __forceinline__ void slice_round(double *r, int *q, int bits) {
   }
 }
 
-// A slices, row-major [s][mp][kp]: one thread per 4 consecutive elements of
-// a row, so a wave reads 2 KB and writes 64 * 4 * ESZ bytes per slice
-// contiguously.
+// Steps 1 and 2 for A in one pass: one workgroup per (padded) row finds the
+// row's exponent and slices it, so A is read from HBM once.  A thread owns
+// quads (4 consecutive k) tid, tid+256, ...; rows up to 4096 long stay in
+// registers between the two passes, longer rows are read again (from L2).
 template <int ESZ>
-__global__ void slice_rows_kernel(const double *A, int64_t lda, int m, int k, int mp, int64_t kp,
-                                  const int *E, int s, int bits, unsigned char *out) {
+__global__ __launch_bounds__(256) void slice_rows_exp_kernel(const double *A, int64_t lda, int m,
+                                                             int k, int mp, int64_t kp, int *E,
+                                                             int s, int bits, unsigned char *out) {
+  constexpr int QPT = 4;  // quads per thread held in registers
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const bool live = i < m;
+  const double *row = A + (int64_t)(live ? i : 0) * lda;
   const int64_t quads = kp / 4;
-  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (id >= (int64_t)mp * quads) return;
-  const int i = (int)(id / quads);
-  const int64_t c0 = (id % quads) * 4;
-  const int ei = E[i];
-  double r[4];
+  const bool regs = quads <= 256 * QPT;
+  auto load = [&](int64_t kk) { return (live && kk < k) ? row[kk] : 0.0; };
+  double x[QPT][4];
+  int e = INT_MIN;
+  for (int64_t q0 = 0; q0 < quads; q0 += 256 * QPT) {
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int64_t kk = c0 + e;
-    const double x = (i < m && kk < k) ? A[(int64_t)i * lda + kk] : 0.0;
-    r[e] = ldexp(x, -ei);
+    for (int j = 0; j < QPT; ++j) {
+      const int64_t qd = q0 + tid + 256 * j;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double val = qd < quads ? load(qd * 4 + v) : 0.0;
+        x[j][v] = val;
+        e = max(e, exp_of(val));
+      }
+    }
   }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) e = max(e, __shfl_xor(e, off));
+  __shared__ int red[4];
+  if ((tid & 63) == 0) red[tid >> 6] = e;
+  __syncthreads();
+  e = max(max(red[0], red[1]), max(red[2], red[3]));
+  const int ei = (e == INT_MIN) ? 0 : e;
+  if (tid == 0) E[i] = ei;
   const int64_t slice_bytes = (int64_t)mp * kp * ESZ;
-  unsigned char *o = out + ((int64_t)i * kp + c0) * ESZ;
-  for (int t = 0; t < s; ++t) {
-    int q[4];
-    slice_round<4>(r, q, bits);
-    if (ESZ == 1) {
-      const unsigned w = (q[0] & 0xff) | ((q[1] & 0xff) << 8) | ((q[2] & 0xff) << 16) |
-                         ((unsigned)(q[3] & 0xff) << 24);
-      *reinterpret_cast<unsigned *>(o + t * slice_bytes) = w;
-    } else {
-      uint2 w;
-      w.x = SlicePack<2>::bf16_bits(q[0]) | (SlicePack<2>::bf16_bits(q[1]) << 16);
-      w.y = SlicePack<2>::bf16_bits(q[2]) | (SlicePack<2>::bf16_bits(q[3]) << 16);
-      *reinterpret_cast<uint2 *>(o + t * slice_bytes) = w;
+  for (int64_t q0 = 0; q0 < quads; q0 += 256 * QPT) {
+#pragma unroll
+    for (int j = 0; j < QPT; ++j) {
+      const int64_t qd = q0 + tid + 256 * j;
+      if (qd >= quads) continue;
+      double r[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) r[v] = ldexp(regs ? x[j][v] : load(qd * 4 + v), -ei);
+      unsigned char *o = out + ((int64_t)i * kp + qd * 4) * ESZ;
+      for (int t = 0; t < s; ++t) {
+        int q[4];
+        slice_round<4>(r, q, bits);
+        if (ESZ == 1) {
+          const unsigned w = (q[0] & 0xff) | ((q[1] & 0xff) << 8) | ((q[2] & 0xff) << 16) |
+                             ((unsigned)(q[3] & 0xff) << 24);
+          *reinterpret_cast<unsigned *>(o + t * slice_bytes) = w;
+        } else {
+          uint2 w;
+          w.x = SlicePack<2>::bf16_bits(q[0]) | (SlicePack<2>::bf16_bits(q[1]) << 16);
+          w.y = SlicePack<2>::bf16_bits(q[2]) | (SlicePack<2>::bf16_bits(q[3]) << 16);
+          *reinterpret_cast<uint2 *>(o + t * slice_bytes) = w;
+        }
+      }
     }
   }
 }
@@ -160,7 +169,7 @@ __global__ void slice_rows_kernel(const double *A, int64_t lda, int m, int k, in
 // a 64 x 64 block of B is transposed through LDS.
 template <int ESZ>
 __global__ __launch_bounds__(256) void slice_cols_kernel(const double *B, int64_t ldb, int k, int n,
-                                                         int np, int64_t kp, const int *F, int s,
+                                                         int np, int64_t kp, int *F, int s,
                                                          int bits, unsigned char *out) {
   __shared__ double T[64][65];
   const int64_t kblocks = kp / 64;
@@ -176,7 +185,12 @@ __global__ __launch_bounds__(256) void slice_cols_kernel(const double *B, int64_
   __syncthreads();
   const int jj = tid >> 2, kq = tid & 3;  // column, 16-long k range (4 lanes per column)
   const int j = j0 + jj;
-  const int fj = F[j];
+  // F[j] still holds INT_MIN for an all-zero (or padding) column: its scale
+  // is 0, and the first k-block of the column stores that back for the
+  // product kernel's epilogue.
+  const int fraw = F[j];
+  const int fj = fraw == INT_MIN ? 0 : fraw;
+  if (k0 == 0 && kq == 0 && fraw == INT_MIN) F[j] = 0;
   double r[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) r[e] = ldexp(T[kq * 16 + e][jj], -fj);
@@ -720,8 +734,6 @@ int split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, const d
   const int bits = split_bits(algo);
   const int mp = (int)L.mp, np = (int)L.np;
 
-  hipLaunchKernelGGL(row_exp_kernel, dim3((unsigned)ceil_div(mp, 4)), dim3(256), 0, s, A, lda,
-                     (int)m, (int)k, mp, E);
   hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)ceil_div(np, 256)), dim3(256), 0, s, F, np,
                      INT_MIN);
   if (n > 0 && k > 0) {
@@ -730,25 +742,22 @@ int split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, const d
                        dim3((unsigned)ceil_div(n, 256), (unsigned)std::min<int64_t>(nchunks, 4096)),
                        dim3(256), 0, s, B, ldb, (int)k, (int)n, F);
   }
-  hipLaunchKernelGGL(col_exp_finish_kernel, dim3((unsigned)ceil_div(np, 256)), dim3(256), 0, s, F,
-                     (int)n, np);
   MG_HIP_TRY(hipGetLastError());
 
   unsigned char *As = w + L.a_off, *Bs = w + L.b_off;
-  const int64_t rthreads = L.mp * (L.kp / 4);
   const int64_t cblocks = (L.np / 64) * (L.kp / 64);
-  if (rthreads / 256 + 1 > INT32_MAX || cblocks > INT32_MAX) {
+  if (cblocks > INT32_MAX) {
     set_error("split operands too large");
     return MG_ERR_INVALID_ARG;
   }
   if (algo == MG_SPLIT_BF16) {
-    hipLaunchKernelGGL(slice_rows_kernel<2>, dim3((unsigned)ceil_div(rthreads, 256)), dim3(256), 0,
-                       s, A, lda, (int)m, (int)k, mp, L.kp, E, slices, bits, As);
+    hipLaunchKernelGGL(slice_rows_exp_kernel<2>, dim3((unsigned)mp), dim3(256), 0, s, A, lda,
+                       (int)m, (int)k, mp, L.kp, E, slices, bits, As);
     hipLaunchKernelGGL(slice_cols_kernel<2>, dim3((unsigned)cblocks), dim3(256), 0, s, B, ldb,
                        (int)k, (int)n, np, L.kp, F, slices, bits, Bs);
   } else {
-    hipLaunchKernelGGL(slice_rows_kernel<1>, dim3((unsigned)ceil_div(rthreads, 256)), dim3(256), 0,
-                       s, A, lda, (int)m, (int)k, mp, L.kp, E, slices, bits, As);
+    hipLaunchKernelGGL(slice_rows_exp_kernel<1>, dim3((unsigned)mp), dim3(256), 0, s, A, lda,
+                       (int)m, (int)k, mp, L.kp, E, slices, bits, As);
     hipLaunchKernelGGL(slice_cols_kernel<1>, dim3((unsigned)cblocks), dim3(256), 0, s, B, ldb,
                        (int)k, (int)n, np, L.kp, F, slices, bits, Bs);
   }

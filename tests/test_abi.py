@@ -48,8 +48,8 @@ def test_version_and_cfgs():
         assert mg.tile_cfg_info(c, mg.F32)["bk"] == 2 * info["bk"]
     with pytest.raises(mg.MgError):
         mg.tile_cfg_info(99)
-    assert mg.pick_tile_cfg(8192, 8192, 8192) == 18
-    assert mg.pick_tile_cfg(2048, 2048, 2048) == 17
+    assert mg.pick_tile_cfg(8192, 8192, 8192) == 21
+    assert mg.pick_tile_cfg(2048, 2048, 2048) == 21
     assert 0 <= mg.pick_tile_cfg(16, 16, 16) < mg.num_tile_cfgs()
 
 

@@ -486,6 +486,9 @@ struct SplitDmaShape {
   static constexpr int RPI = 64 / CPR;        // rows per DMA instruction (1 KB)
   static constexpr int IA = BM / RPI / WAVES;  // DMA instructions per wave, A
   static constexpr int IB = BN / RPI / WAVES;
+  // Two workgroups per CU when their rings fit: the register budget must
+  // then allow 2*WAVES/4 wavefronts per SIMD (second __launch_bounds__ value).
+  static constexpr int MINW = 2 * LDS_BYTES <= 160 * 1024 ? (WAVES >= 2 ? WAVES / 2 : 1) : 1;
   static_assert(SB == 64 || SB == 128, "stage depth");
   static_assert(IA * RPI * WAVES == BM && IB * RPI * WAVES == BN, "whole DMA rows per wave");
   static_assert(NS >= 2, "at least double buffering");
@@ -511,7 +514,8 @@ __device__ __forceinline__ void dma16(const unsigned char *src, unsigned char *l
 
 // `a.seg_stages` and `a.total_stages` count SB-byte stages here.
 template <int ALGO, int WGM, int WGN, int FMW, int FNW, int NS, int SB>
-__global__ __launch_bounds__((SplitDmaShape<WGM, WGN, FMW, FNW, NS, SB>::THREADS), 1) void
+__global__ __launch_bounds__((SplitDmaShape<WGM, WGN, FMW, FNW, NS, SB>::THREADS),
+                             (SplitDmaShape<WGM, WGN, FMW, FNW, NS, SB>::MINW)) void
 split_gemm_dma_kernel(SplitArgs a, int tiles_m, int tiles_n) {
   typedef SplitMma<ALGO> M;
   typedef typename M::acc_t Acc;
@@ -765,7 +769,7 @@ int split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, const d
   return MG_OK;
 }
 
-int split_num_cfgs() { return 12; }
+int split_num_cfgs() { return 15; }
 
 // Product-kernel work division (measured on MI355X at n = 4096): the 256x256
 // direct-to-LDS tile once every CU gets one, then the 128x256 one, else the
@@ -828,6 +832,9 @@ int split_multiply(int algo, int slices, int64_t m, int64_t n, int64_t k, double
     case 9: return launch_split_dma<2, 4, 8, 4, 4, 64>(algo, a, L, s);  // 256x256, 8 waves, 4 x 64 B
     case 10: return launch_split_dma<4, 2, 4, 8, 4, 64>(algo, a, L, s);  // 256x256, 8 waves, 4 x 64 B
     case 11: return launch_split_dma<2, 4, 8, 4, 2, 128>(algo, a, L, s);  // 256x256, 8 waves, 2 x 128 B
+    case 12: return launch_split_dma<2, 4, 4, 2, 2, 128>(algo, a, L, s);  // 128x128, 8 waves, 2 x 128 B
+    case 13: return launch_split_dma<2, 2, 4, 4, 2, 128>(algo, a, L, s);  // 128x128, 4 waves, 2 x 128 B
+    case 14: return launch_split_dma<2, 4, 4, 2, 3, 128>(algo, a, L, s);  // 128x128, 8 waves, 3 x 128 B
   }
   set_error("unknown split cfg %d", cfg);
   return MG_ERR_INVALID_ARG;

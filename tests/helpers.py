@@ -14,7 +14,7 @@ NATIVE_CFGS = 22
 # Of those, the ones that load 16-byte aligned operands straight into LDS.
 DMA_CFGS = (14, 15, 16, 17, 18, 19, 20, 21)
 # Split product-kernel work divisions (mg_split_num_cfgs), all covered likewise.
-SPLIT_CFGS = 12
+SPLIT_CFGS = 15
 
 U64 = 2.0 ** -53  # unit roundoff of FP64
 U32 = 2.0 ** -24

@@ -4,12 +4,14 @@
 // beta_i C_i into a device work list of macro-tiles (each record carries its
 // problem's arguments, tile coordinates and a tile class from the tuning
 // table), sorted longest first.  One persistent kernel of (CUs x occupancy)
-// workgroups walks the list round-robin (workgroup b takes tiles b, b+G,
-// b+2G, ...: with the list in decreasing cost this deals the expensive tiles
-// out evenly) and runs the same per-tile code as the single-problem kernel,
+// workgroups deals the list out in rounds of G tiles, alternating direction
+// (workgroup b takes tile b of round 0, G-1-b of round 1, ...: with the list
+// in decreasing cost every workgroup ends up with about the same work) and
+// runs the same per-tile arithmetic as the single-problem kernel,
 // so a problem's result does not depend on what else is in the batch.  Each
-// workgroup loads its next record while it computes the current tile.  The
-// launch is captured once in a HIP graph and replayed.
+// workgroup streams its tiles' k-steps through an LDS ring that is filled two
+// steps ahead, across tile boundaries.  The launch is captured once in a HIP
+// graph and replayed.
 //
 // In the paper's terms (Section 3.2): blocks are independent and are never
 // synchronised with each other; they share nothing but the read-only list.
@@ -134,21 +136,6 @@ __device__ __forceinline__ void gd_wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
 }
 
-// Waits until at most 4*q vector memory operations of this wave are pending.
-__device__ __forceinline__ void gd_wait_dyn(int q) {
-  switch (q) {
-    case 0: gd_wait_vmcnt<0>(); break;
-    case 1: gd_wait_vmcnt<4>(); break;
-    case 2: gd_wait_vmcnt<8>(); break;
-    case 3: gd_wait_vmcnt<12>(); break;
-    case 4: gd_wait_vmcnt<16>(); break;
-    case 5: gd_wait_vmcnt<20>(); break;
-    case 6: gd_wait_vmcnt<24>(); break;
-    case 7: gd_wait_vmcnt<28>(); break;
-    default: gd_wait_vmcnt<32>(); break;
-  }
-}
-
 __device__ __forceinline__ void gd_dma4(const void *src, unsigned char *lds_dst) {
   __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds_dst, 4, 0,
                                    0);
@@ -178,7 +165,7 @@ template <typename T>
 __device__ __forceinline__ int gd_b_krow(int wave, int ib, int u, int lane, int bn) {
   constexpr int ESZ = sizeof(T), VEC = 16 / ESZ;
   const int o = (wave * ib + u) * 256 + lane * 4;
-  return (o >> 4) / bn * VEC + (o & 15) / ESZ;  // kc*VEC + e
+  return ((o >> 4) >> (bn == 64 ? 6 : 5)) * VEC + (o & 15) / ESZ;  // kc*VEC + e
 }
 
 template <typename T>
@@ -252,7 +239,7 @@ __device__ __forceinline__ int gd_issue(const GdSlots<T> &sl, const GemmArgs<T> 
 // `kvalid` k of the step belong to the problem; the rest is zeroed on both
 // operands (values read from clamped addresses never reach the sums).
 template <typename T, int BM, int BN, bool TAIL>
-__device__ __forceinline__ void gd_compute(typename Mfma<T>::acc_t (&acc)[2][2],
+__device__ __forceinline__ void gd_compute(typename Mfma<T>::acc_t (&acc)[BM / 32][BN / 32],
                                            const unsigned char *As, const unsigned char *Bs,
                                            int wave, int lane, int kvalid) {
   typedef Mfma<T> M;
@@ -293,17 +280,9 @@ __device__ __forceinline__ void gd_compute(typename Mfma<T>::acc_t (&acc)[2][2],
 }
 
 template <typename T, int BM, int BN>
-__device__ __forceinline__ void gd_step(typename Mfma<T>::acc_t (&acc)[2][2],
-                                        const unsigned char *As, const unsigned char *Bs,
-                                        int wave, int lane, int kvalid) {
-  if (kvalid >= 128 / (int)sizeof(T)) gd_compute<T, BM, BN, false>(acc, As, Bs, wave, lane, kvalid);
-  else gd_compute<T, BM, BN, true>(acc, As, Bs, wave, lane, kvalid);
-}
-
-template <typename T, int BM, int BN>
 __device__ __forceinline__ void gd_store(const GTileRec<T> &t,
-                                         const typename Mfma<T>::acc_t (&acc)[2][2], int wave,
-                                         int lane) {
+                                         const typename Mfma<T>::acc_t (&acc)[BM / 32][BN / 32],
+                                         int wave, int lane) {
   constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
   const int m0 = t.tm * BM + (wave >> 1) * WM, n0 = t.tn * BN + (wave & 1) * WN;
   if ((t.cls >> 5) & 1) Epilogue<T, true>::template store<FM, FN>(t.g, acc, m0, n0, lane);
@@ -321,97 +300,120 @@ __device__ __forceinline__ GTileRec<T> gd_record(const GTileRec<T> *tiles, int w
   return r;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kTileThreads, 3) void grouped_dma_kernel(
-    const GTileRec<T> *__restrict__ tiles, int ntiles) {
-  typedef typename Mfma<T>::acc_t Acc;
-  constexpr int BK = 128 / (int)sizeof(T);
-  extern __shared__ __align__(16) unsigned char lds[];
-  // wave index made uniform so LDS destinations (M0) are scalar arithmetic
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int G = (int)gridDim.x;
+// Load cursor of a workgroup: walks the same tiles as the compute side,
+// NS-1 k-steps ahead, and remembers how many DMA instructions each issued
+// but unconsumed step has (at most two with a 3-stage ring).
+// Tile of workgroup b in dealing round r: rounds alternate direction
+// (b, then G-1-b), so with the list in decreasing cost every workgroup gets
+// a fair share of the expensive and of the cheap tiles.  Past the list:
+// ntiles.
+__device__ __forceinline__ int gd_deal(int r, int b, int G, int ntiles) {
+  if ((int64_t)r * G >= ntiles) return ntiles;
+  const int w = r * G + ((r & 1) ? G - 1 - b : b);
+  return w < ntiles ? w : ntiles;
+}
 
-  // Load cursor: tile index, record, next k-step; scale-only tiles have no steps.
-  int lw = blockIdx.x, lkt = 0;
-  GTileRec<T> L{};
-  if (lw < ntiles) L = gd_record(tiles, lw);
-  while (lw < ntiles && (L.cls & 15) == kScaleCls) {
-    lw += G;
-    if (lw < ntiles) L = gd_record(tiles, lw);
-  }
+template <typename T>
+struct GdLoader {
+  const GTileRec<T> *tiles;
+  int ntiles, G, lr, lw, lkt, li;
+  GTileRec<T> L;
   GdSlots<T> sl;
-  if (lw < ntiles) {
-    const int c = L.cls & 15;
-    gd_setup<T>(sl, L.g, c, L.tm * gd_bm(c), L.tn * gd_bn(c), wave, lane);
+  unsigned char *lds;
+  int wave, lane;
+  int q0, q1;  // DMA counts of the oldest and the next unconsumed step (0: none)
+
+  __device__ __forceinline__ void next_tile() {
+    do {
+      lw = gd_deal(++lr, (int)blockIdx.x, G, ntiles);
+      if (lw < ntiles) L = gd_record(tiles, lw);
+    } while (lw < ntiles && (L.cls & 15) == kScaleCls);
+    if (lw < ntiles) {
+      const int c = L.cls & 15;
+      gd_setup<T>(sl, L.g, c, L.tm * gd_bm(c), L.tn * gd_bn(c), wave, lane);
+    }
   }
-  // Pending steps: DMA counts/4 in 4-bit fields, oldest lowest; their sum.
-  unsigned pend = 0;
-  int nfl = 0, psum = 0, li = 0;
-  auto issue_next = [&]() {
-    if (lw >= ntiles) return;
+  // Issues the next k-step of the stream; returns its DMA count (0 if none).
+  __device__ __forceinline__ int issue() {
+    constexpr int BK = 128 / (int)sizeof(T);
+    if (lw >= ntiles) return 0;
     const int cnt = gd_issue<T>(sl, L.g, L.cls & 15, lkt * BK, lds + (li % kGdNS) * kGdStage,
                                 wave, lane);
-    pend |= (unsigned)(cnt >> 2) << (4 * nfl);
-    ++nfl;
-    psum += cnt >> 2;
     ++li;
     if (++lkt * BK >= L.g.k) {
       lkt = 0;
-      do {
-        lw += G;
-        if (lw < ntiles) L = gd_record(tiles, lw);
-      } while (lw < ntiles && (L.cls & 15) == kScaleCls);
-      if (lw < ntiles) {
-        const int c = L.cls & 15;
-        gd_setup<T>(sl, L.g, c, L.tm * gd_bm(c), L.tn * gd_bn(c), wave, lane);
-      }
+      next_tile();
     }
-  };
-#pragma unroll
-  for (int q = 0; q < kGdNS - 1; ++q) issue_next();
+    return cnt;
+  }
+};
 
-  Acc acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = Acc{};
+// Waits until at most `n` (the next step's DMA count) vector memory
+// operations of this wave are outstanding: the current step has landed.
+__device__ __forceinline__ void gd_wait_next(int n) {
+  if (n >= 16) gd_wait_vmcnt<16>();
+  else if (n >= 12) gd_wait_vmcnt<12>();
+  else if (n >= 8) gd_wait_vmcnt<8>();
+  else gd_wait_vmcnt<0>();
+}
 
-  int cw = blockIdx.x, ckt = 0, t = 0;
-  GTileRec<T> C{};
-  if (cw < ntiles) C = gd_record(tiles, cw);
-  for (;;) {
-    while (cw < ntiles && (C.cls & 15) == kScaleCls) {
-      scale_tile<T>(C.g, C.tm * kScaleTile, C.tn * kScaleTile);
-      cw += G;
-      if (cw < ntiles) C = gd_record(tiles, cw);
-    }
-    if (cw >= ntiles) break;
-    // Step t has landed once only the later steps' DMAs may still be pending.
-    gd_wait_dyn(psum - (int)(pend & 15));
+// All k-steps of one tile of class (BM, BN), then its epilogue; `t` counts
+// the workgroup's consumed steps (ring position).
+template <typename T, int BM, int BN>
+__device__ __forceinline__ void gd_run_tile(GdLoader<T> &ld, const GTileRec<T> &C, int &t) {
+  typedef typename Mfma<T>::acc_t Acc;
+  constexpr int BK = 128 / (int)sizeof(T);
+  constexpr int FM = BM / 32, FN = BN / 32;
+  Acc acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = Acc{};
+  const int KT = (C.g.k + BK - 1) / BK;
+  for (int kt = 0; kt < KT; ++kt) {
+    gd_wait_next(ld.q1);
     __builtin_amdgcn_s_barrier();
-    issue_next();
-    const unsigned char *As = lds + (t % kGdNS) * kGdStage;
+    const int cnew = ld.issue();
+    const unsigned char *As = ld.lds + (t % kGdNS) * kGdStage;
     const unsigned char *Bs = As + kGdStageA;
-    const int c = C.cls & 15, kvalid = C.g.k - ckt * BK;
-    if (c == 0) gd_step<T, 64, 64>(acc, As, Bs, wave, lane, kvalid);
-    else if (c == 1) gd_step<T, 64, 32>(acc, As, Bs, wave, lane, kvalid);
-    else gd_step<T, 32, 32>(acc, As, Bs, wave, lane, kvalid);
-    psum -= (int)(pend & 15);
-    pend >>= 4;
-    --nfl;
+    const int kvalid = C.g.k - kt * BK;
+    if (kvalid >= BK) gd_compute<T, BM, BN, false>(acc, As, Bs, ld.wave, ld.lane, kvalid);
+    else gd_compute<T, BM, BN, true>(acc, As, Bs, ld.wave, ld.lane, kvalid);
+    ld.q0 = ld.q1;
+    ld.q1 = cnew;
     ++t;
-    if (++ckt * BK >= C.g.k) {
-      if (c == 0) gd_store<T, 64, 64>(C, acc, wave, lane);
-      else if (c == 1) gd_store<T, 64, 32>(C, acc, wave, lane);
-      else gd_store<T, 32, 32>(C, acc, wave, lane);
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = Acc{};
-      ckt = 0;
-      cw += G;
-      if (cw < ntiles) C = gd_record(tiles, cw);
-    }
+  }
+  gd_store<T, BM, BN>(C, acc, ld.wave, ld.lane);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTileThreads, 3) void grouped_dma_kernel(
+    const GTileRec<T> *__restrict__ tiles, int ntiles) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  GdLoader<T> ld;
+  ld.tiles = tiles;
+  ld.ntiles = ntiles;
+  ld.G = (int)gridDim.x;
+  ld.lds = lds;
+  // wave index made uniform so LDS destinations (M0) are scalar arithmetic
+  ld.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  ld.lane = threadIdx.x & 63;
+  ld.lkt = 0;
+  ld.li = 0;
+  ld.lr = -1;
+  ld.next_tile();  // first tile with k-steps
+  ld.q0 = ld.issue();
+  ld.q1 = ld.issue();
+
+  int cr = 0, t = 0;
+  for (int cw = gd_deal(0, blockIdx.x, ld.G, ntiles); cw < ntiles;
+       cw = gd_deal(++cr, blockIdx.x, ld.G, ntiles)) {
+    const GTileRec<T> C = gd_record(tiles, cw);
+    const int c = C.cls & 15;
+    if (c == kScaleCls) scale_tile<T>(C.g, C.tm * kScaleTile, C.tn * kScaleTile);
+    else if (c == 0) gd_run_tile<T, 64, 64>(ld, C, t);
+    else if (c == 1) gd_run_tile<T, 64, 32>(ld, C, t);
+    else gd_run_tile<T, 32, 32>(ld, C, t);
   }
 }
 

@@ -120,6 +120,9 @@ void simulate_batch(Server *S, Lane &L, int64_t batch_id) {
   L.sim_done_ns = start + dur;
 }
 
+// Native requests with m*n*k at least this (1024^3) run as their own launch.
+constexpr double kDirectMNK = 1073741824.0;
+
 // Enqueues one batch on lane L (no lock held; L is owned by this batch).
 void launch_batch(Server *S, Lane &L, int64_t batch_id) {
   if (S->o.simulate) {
@@ -129,11 +132,18 @@ void launch_batch(Server *S, Lane &L, int64_t batch_id) {
   const int64_t t = now_ns();
   const int nb = (int)L.batch.size();
   std::vector<mg_problem> p64, p32;
+  std::vector<Req *> direct;
   for (Req *q : L.batch) {
     q->res.t_launch_ns = t;
     q->res.batch_id = batch_id;
     q->res.batch_size = nb;
-    if (q->r.algo == MG_NATIVE) (q->r.dtype == MG_F64 ? p64 : p32).push_back(q->r.p);
+    if (q->r.algo != MG_NATIVE) continue;
+    const mg_problem &p = q->r.p;
+    // Large problems fill the GPU on their own and run faster with the
+    // single-problem work divisions than as 64x64 tiles of the grouped
+    // kernel; the choice depends only on the request's own shape.
+    if ((double)p.m * (double)p.n * (double)p.k >= kDirectMNK) direct.push_back(q);
+    else (q->r.dtype == MG_F64 ? p64 : p32).push_back(p);
   }
   const mg_tune_table *tab = S->has_table ? &S->table : nullptr;
   WorkList w64, w32;
@@ -161,6 +171,12 @@ void launch_batch(Server *S, Lane &L, int64_t batch_id) {
   }
   for (Req *q : L.batch)
     if (q->r.algo == MG_NATIVE && rc != MG_OK) q->res.status = rc;
+  for (Req *q : direct) {
+    const mg_problem &p = q->r.p;
+    const int r2 = gemm_native(q->r.dtype, pick_tile_cfg(q->r.dtype, p.m, p.n, p.k), p.m, p.n,
+                               p.k, p.alpha, p.A, p.lda, p.B, p.ldb, p.beta, p.C, p.ldc, L.s);
+    if (r2 != MG_OK) q->res.status = r2;
+  }
   for (Req *q : L.batch) {
     if (q->r.algo == MG_NATIVE) continue;
     const mg_problem &p = q->r.p;

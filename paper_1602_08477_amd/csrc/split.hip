@@ -775,9 +775,11 @@ int split_num_cfgs() { return 15; }
 // direct-to-LDS tile once every CU gets one, then the 128x256 one, else the
 // register-staged 128x128 tile.
 int split_pick_cfg(int algo, int64_t mp, int64_t np) {
-  // INT8: the 16-wave 256x256 tile once it fills the chip; BF16 keeps its
-  // FP32 chunk accumulators in registers and runs best with 8 waves.
+  // INT8: the 16-wave 256x256 tile once it fills the chip.  BF16 keeps its
+  // FP32 chunk accumulators in registers: 128x128 tiles on 8 waves, two
+  // workgroups per CU.
   if (algo == MG_SPLIT_I8 && (mp / 256) * (np / 256) >= 256) return 4;
+  if (algo == MG_SPLIT_BF16 && (mp / 128) * (np / 128) >= 512) return 12;
   if ((mp / 128) * (np / 256) >= 256) return 2;
   return 0;
 }

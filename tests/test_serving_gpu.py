@@ -156,3 +156,35 @@ def test_invalid_request_rejected_before_queueing():
         assert mg.lib().mg_gemm_submit(srv._h, ctypes.byref(r), ctypes.byref(t)) \
             == mg.ERR_UNSUPPORTED
         assert srv.stats()["submitted"] == 0
+
+
+def test_large_native_requests_run_direct_and_match():
+    """Native requests of at least 1024^3 multiply-adds run as their own
+    launch inside a batch; the result equals the library call alone (bit for
+    bit) and the oracle on sampled outputs."""
+    m, n, k = 1100, 1030, 1000
+    A = synth.matrix(97, 0, m, k, device="cuda")
+    B = synth.matrix(97, 1, k, n, device="cuda")
+    C = synth.matrix(97, 2, m, n, device="cuda")
+    C0 = C.clone()
+    small = [(synth.matrix(98 + i, 0, 64, 64, device="cuda"),
+              synth.matrix(98 + i, 1, 64, 64, device="cuda"),
+              torch.zeros(64, 64, dtype=torch.float64, device="cuda")) for i in range(4)]
+    with mg.Server(n_streams=1, max_batch=16) as srv:
+        ts = [srv.submit(a, b, c) for a, b, c in small]
+        tl = srv.submit(A, B, C, 1.0, 1.0)
+        for t in ts:
+            assert srv.wait(t)["status"] == mg.OK
+        assert srv.wait(tl)["status"] == mg.OK
+    alone = C0.clone()
+    mg.gemm(A, B, alone, 1.0, 1.0)
+    torch.cuda.synchronize()
+    assert torch.equal(alone, C)
+    rows = np.array([0, 1, 517, m - 1])
+    cols = np.array([0, 3, 640, n - 1])
+    ref = oracle.dgemm_sampled(1.0, A.cpu().numpy(), B.cpu().numpy(), 1.0, C0.cpu().numpy(),
+                               rows, cols)
+    got = C.cpu().numpy()[np.ix_(rows, cols)]
+    assert oracle.rel_fro_err(got, ref) <= 1e-13
+    for a, b, c in small:
+        assert torch.allclose(c, a @ b, rtol=0, atol=1e-12)

@@ -45,6 +45,12 @@ struct DmaShape {
   static_assert(FM >= 1 && FN >= 1 && WM % 16 == 0 && WN % 16 == 0, "16x16 blocks per wave");
   static_assert(CPB >= 8 && (CPB & (CPB - 1)) == 0, "B rows of 2^j >= 8 chunks");
   static_assert(NS >= 2 && LDS_BYTES <= 160 * 1024, "ring fits in LDS");
+  // Wavefronts per SIMD the register allocation must leave room for (the
+  // second __launch_bounds__ value): as many workgroups as the LDS ring
+  // allows per CU, counted up to 2 per SIMD so large register tiles (a
+  // 4-wave 128x128 tile holds 128 FP64 accumulators per lane) still get 256.
+  static constexpr int WGS_PER_CU = (int)((160 * 1024) / LDS_BYTES);
+  static constexpr int MINW = WGS_PER_CU * WAVES / 4 >= 2 ? 2 : 1;
 };
 
 __device__ __forceinline__ int dma_swz_a(int row, int c) { return c ^ ((row >> 1) & 7); }

@@ -23,7 +23,8 @@ __global__ __launch_bounds__((TileShape<T, BM, BN, WGM, WGN, BKM>::THREADS)) voi
 }
 
 template <typename T, int BM, int BN, int WGM, int WGN, int NS>
-__global__ __launch_bounds__((DmaShape<T, BM, BN, WGM, WGN, NS>::THREADS)) void gemm_dma_kernel(
+__global__ __launch_bounds__((DmaShape<T, BM, BN, WGM, WGN, NS>::THREADS),
+                             (DmaShape<T, BM, BN, WGM, WGN, NS>::MINW)) void gemm_dma_kernel(
     GemmArgs<T> g, int tiles_m, int tiles_n) {
   extern __shared__ __align__(16) unsigned char lds[];
   int tm, tn;
@@ -47,7 +48,7 @@ __global__ void scale_kernel(T *C, int64_t ldc, int m, int n, T beta) {
 struct CfgDesc {
   int bm, bn, wgm, wgn, bkm;
 };
-// Work divisions 0-13 stage A and B through registers; 14-21 load them
+// Work divisions 0-13 stage A and B through registers; 14-24 load them
 // straight into an LDS ring (16-byte aligned operands only: otherwise a
 // register-staged division of the same macro-tile runs).
 // Work divisions: macro-tile, wavefront grid, k-step multiplier.
@@ -58,7 +59,8 @@ constexpr CfgDesc kCfgs[] = {{128, 128, 2, 2, 1}, {128, 64, 2, 2, 1}, {64, 64, 2
                              {256, 128, 4, 4, 1}, {128, 128, 4, 2, 2},  {64, 64, 2, 2, 1},
                              {64, 32, 2, 2, 1},   {128, 64, 2, 2, 1},  {128, 128, 2, 4, 1},
                              {256, 128, 4, 4, 1},  {32, 32, 2, 2, 1},   {64, 64, 4, 2, 1},
-                             {128, 128, 2, 4, 1}};
+                             {128, 128, 2, 4, 1},  {128, 128, 2, 2, 1}, {64, 64, 2, 2, 1},
+                             {64, 32, 2, 2, 1}};
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 
 template <typename T, int BM, int BN, bool VEC_OK, int WGM = 2, int WGN = 2, int BKM = 1>
@@ -144,6 +146,13 @@ int launch_cfg(int cfg, const GemmArgs<T> &g, hipStream_t s) {
     case 21:
       return VEC_OK ? launch_dma<T, 128, 128, 2, 4, 2>(g, s)
                     : launch_one<T, 128, 128, VEC_OK, 4, 2, 2>(g, s);
+    case 22:
+      return VEC_OK ? launch_dma<T, 128, 128, 2, 2, 2>(g, s)
+                    : launch_one<T, 128, 128, VEC_OK, 4, 2, 2>(g, s);
+    case 23:
+      return VEC_OK ? launch_dma<T, 64, 64, 2, 2, 2>(g, s) : launch_one<T, 64, 64, VEC_OK>(g, s);
+    case 24:
+      return VEC_OK ? launch_dma<T, 64, 32, 2, 2, 3>(g, s) : launch_one<T, 64, 32, VEC_OK>(g, s);
   }
   set_error("unknown tile cfg %d", cfg);
   return MG_ERR_INVALID_ARG;
@@ -201,18 +210,19 @@ int tile_cfg_info(int dtype, int cfg, int *bm, int *bn, int *bk, int *threads) {
 }
 
 int pick_tile_cfg(int dtype, int64_t m, int64_t n, int64_t k) {
-  (void)dtype;
   (void)k;
-  // Measured on MI355X (FP64 and FP32, 16-byte aligned operands): 128x128
-  // tiles on 8 wavefronts with a 2-stage direct-load ring (two workgroups per
-  // CU) once every CU gets a tile (n >= 2048; 90 % of FP64 peak at 8192),
-  // the 64x32 ring at two tiles per CU (n = 1024), the 32x32 ring at one
-  // (n = 512), then the small register-staged tiles.  Unaligned operands run
-  // a register-staged division of the same macro-tile.
+  // Measured on MI355X (16-byte aligned operands): 128x128 tiles with a
+  // 2-stage direct-load ring and two workgroups per CU once every CU gets a
+  // tile (n >= 2048; FP64 on 8 wavefronts: 90 % of peak at 8192; FP32 on 4
+  // wavefronts once there are four tiles per CU), then the 64x64 ring
+  // (n = 1024) and the 32x32 ring (n = 512), then the small register-staged
+  // tiles.  Unaligned operands run a register-staged division of the same
+  // macro-tile.
   auto tiles = [&](int c) { return ceil_div(m, kCfgs[c].bm) * ceil_div(n, kCfgs[c].bn); };
   const int64_t cus = 256;
+  if (dtype == MG_F32 && tiles(22) >= 4 * cus) return 22;
   if (tiles(21) >= cus) return 21;
-  if (tiles(15) >= 2 * cus) return 15;
+  if (tiles(23) >= cus) return 23;
   if (tiles(19) >= cus) return 19;
   if (tiles(2) >= 2 * cus) return 2;
   if (tiles(3) >= 2 * cus) return 3;

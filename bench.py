@@ -42,6 +42,7 @@ METRIC = "GEMM TFLOP/s & %peak: FP64 vs split-prec at 1e-12 rel err; p99 latency
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dgemm_f64_n8192.json")
 KERNEL_SOURCES = ["paper_1602_08477_amd/csrc/gemm_tile.h",
                   "paper_1602_08477_amd/csrc/gemm_dma.h",
+                  "paper_1602_08477_amd/csrc/gemm_launch.h",
                   "paper_1602_08477_amd/csrc/gemm_native.hip",
                   "paper_1602_08477_amd/csrc/common.h"]
 
@@ -217,6 +218,42 @@ def bench_sizes(steps, warmup):
     del flush
     torch.cuda.empty_cache()
     return out
+
+
+def bench_trans(n, steps, warmup):
+    """Operand layouts at the headline shape (m = n = k, alpha = beta = 1):
+    C <- op(A) op(B) + C for op = identity / transpose on each side (mg_gemm_ex
+    with the stored transposed copies), launches timed in rotation with HIP
+    events; each layout's output checked on sampled entries."""
+    import torch
+    import paper_1602_08477_amd as mg
+    import synth
+    seed = synth.config_seed(2)
+    dA = synth.matrix(seed, synth.STREAM_A, n, n, device="cuda")
+    dB = synth.matrix(seed, synth.STREAM_B, n, n, device="cuda")
+    C0 = synth.matrix(seed, synth.STREAM_C, n, n, device="cuda")
+    sA, sB = dA.t().contiguous(), dB.t().contiguous()
+    dC = C0.clone()
+    stream = torch.cuda.current_stream()
+    layouts = [(0, 0), (1, 0), (0, 1), (1, 1)]
+    fns = [lambda ta=ta, tb=tb: mg.gemm_ex(sA if ta else dA, sB if tb else dB, dC, 1.0, 1.0,
+                                          transa=bool(ta), transb=bool(tb))
+           for ta, tb in layouts]
+    per = time_interleaved(fns, steps, warmup, stream)
+    flop = 2.0 * n ** 3
+    out = {}
+    for (ta, tb), fn, p in zip(layouts, fns, per):
+        dC.copy_(C0)
+        fn()
+        torch.cuda.synchronize()
+        ms = float(np.mean(p))
+        out["NT"[ta] + "NT"[tb]] = {
+            "ms": round(ms, 4), "tflops": round(flop / ms / 1e9, 3),
+            "pct_peak": round(100 * flop / ms / 1e9 / FP64_PEAK, 2),
+            "rel_fro_err_sampled": float(f"{sampled_error(dA, dB, C0, dC, 1.0, 1.0, seed):.3e}")}
+    del dA, dB, C0, sA, sB, dC
+    torch.cuda.empty_cache()
+    return {"m": n, "n": n, "k": n, "tile_cfg": mg.pick_tile_cfg(n, n, n), "layouts": out}
 
 
 def bench_split(n, steps, warmup):
@@ -443,7 +480,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--quick", action="store_true", help="headline only (for profiling)")
-    ap.add_argument("--leg", choices=["sizes", "split", "batched", "serving"], default=None,
+    ap.add_argument("--leg", choices=["sizes", "trans", "split", "batched", "serving"],
+                    default=None,
                     help="run only this secondary leg and print its record (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
@@ -465,6 +503,7 @@ def main():
     if args.leg is not None:
         fn = {"split": lambda: bench_split(4096, max(3, args.steps), 1),
               "sizes": lambda: bench_sizes(args.steps, args.warmup),
+              "trans": lambda: bench_trans(args.n, args.steps, args.warmup),
               "batched": lambda: bench_batched(max(3, args.steps)),
               "serving": lambda: bench_serving(args.serve_seconds)}[args.leg]
         print(json.dumps({"leg": args.leg, "record": fn()}), flush=True)
@@ -511,6 +550,8 @@ def main():
     if not args.quick:
         eprint("bench: size sweep")
         rec["sizes"] = bench_sizes(args.steps, args.warmup)
+        eprint("bench: operand layouts")
+        rec["trans"] = bench_trans(n, args.steps, args.warmup)
         eprint("bench: split precision n=4096")
         rec["split"] = bench_split(4096, max(5, args.steps), 2)
         eprint("bench: batched 2000 problems")

@@ -96,6 +96,21 @@ int mg_gemm_cfg(int dtype, int cfg, int64_t m, int64_t n, int64_t k, double alph
 /* The cfg mg_gemm picks for this shape (its work-division rule). */
 int mg_pick_tile_cfg(int dtype, int64_t m, int64_t n, int64_t k);
 
+/* mg_gemm_ex: C <- alpha*op(A)*op(B) + beta*C on the native kernels, with
+ * op(X) = X (trans 0) or its transpose X^T (trans 1).  The paper measures
+ * square row-major operands only (Section 4.2); the transposed layouts run
+ * the same tiles with the stored rows of A^T / B^T staged as k rows / k
+ * columns, so every output sums the same products in the same order as the
+ * plain layout (bit-identical results for the same cfg).
+ *   transa 0: A stored m x k, lda >= k;  1: A stored k x m, lda >= m.
+ *   transb 0: B stored k x n, ldb >= n;  1: B stored n x k, ldb >= k.
+ *   cfg    a work division as in mg_gemm_cfg, or -1 for mg_pick_tile_cfg's.
+ *   dtype  MG_F64 or MG_F32.  Other arguments, special cases and errors as
+ *          mg_gemm (MG_ERR_INVALID_ARG for trans flags other than 0/1). */
+int mg_gemm_ex(int dtype, int cfg, int transa, int transb, int64_t m, int64_t n, int64_t k,
+               double alpha, const void *A, int64_t lda, const void *B, int64_t ldb, double beta,
+               void *C, int64_t ldc, void *stream);
+
 /* ------------------------------------------------ split-precision FP64 --
  * The FP64 product is rebuilt from exact integer slices (not part of the
  * paper, which computes DGEMM natively; the splitting follows Ozaki et al.'s

@@ -69,6 +69,7 @@ def lib() -> ctypes.CDLL:
         gemm_args = [_i64, _i64, _i64, _dbl, _vp, _i64, _vp, _i64, _dbl, _vp, _i64, _vp]
         L.mg_gemm.argtypes = [_int, _int] + gemm_args
         L.mg_gemm_cfg.argtypes = [_int, _int] + gemm_args
+        L.mg_gemm_ex.argtypes = [_int, _int, _int, _int] + gemm_args
         L.mg_split_default_slices.argtypes = [_int]
         L.mg_split_layout_query.argtypes = [_int, _int, _i64, _i64, _i64,
                                             ctypes.POINTER(SplitLayout)]
@@ -150,6 +151,24 @@ def gemm(A, B, C, alpha: float = 1.0, beta: float = 0.0, algo: int = NATIVE,
         check(lib().mg_gemm(dt, algo, m, n, kk, alpha, pa, lda, pb, ldb, beta, pc, ldc, s))
     else:
         check(lib().mg_gemm_cfg(dt, cfg, m, n, kk, alpha, pa, lda, pb, ldb, beta, pc, ldc, s))
+    return C
+
+
+def gemm_ex(A, B, C, alpha: float = 1.0, beta: float = 0.0, transa: bool = False,
+            transb: bool = False, cfg: int | None = None, stream=None):
+    """C <- alpha*op(A)@op(B) + beta*C in place (mg_gemm_ex).  A and B are the
+    stored matrices: A is k x m when transa (m x k otherwise), B is n x k when
+    transb (k x n otherwise).  Returns C."""
+    pa, ar, ac, lda = _mat(A, "A")
+    pb, br, bc, ldb = _mat(B, "B")
+    pc, m, n, ldc = _mat(C, "C")
+    am, k = (ac, ar) if transa else (ar, ac)
+    bk, bn = (bc, br) if transb else (br, bc)
+    if am != m or bn != n or bk != k:
+        raise ValueError("op(A), op(B), C shape mismatch")
+    s = _stream_handle(stream)
+    check(lib().mg_gemm_ex(_dtype_code(C), -1 if cfg is None else cfg, int(transa), int(transb),
+                           m, n, k, alpha, pa, lda, pb, ldb, beta, pc, ldc, s))
     return C
 
 

@@ -30,6 +30,13 @@ void clear_error() { g_err[0] = '\0'; }
 int validate_problem(const char *what, int64_t m, int64_t n, int64_t k, double alpha,
                      const void *A, int64_t lda, const void *B, int64_t ldb, double beta,
                      const void *C, int64_t ldc, int64_t esz) {
+  return validate_problem_op(what, false, false, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                             esz);
+}
+
+int validate_problem_op(const char *what, bool ta, bool tb, int64_t m, int64_t n, int64_t k,
+                        double alpha, const void *A, int64_t lda, const void *B, int64_t ldb,
+                        double beta, const void *C, int64_t ldc, int64_t esz) {
   (void)beta;
   if (m < 0 || n < 0 || k < 0) {
     set_error("%s: negative extent (m=%lld n=%lld k=%lld)", what, (long long)m, (long long)n,
@@ -66,12 +73,15 @@ int validate_problem(const char *what, int64_t m, int64_t n, int64_t k, double a
     set_error("%s: A or B is NULL", what);
     return MG_ERR_INVALID_ARG;
   }
-  if (lda < k) {
-    set_error("%s: lda=%lld < k=%lld", what, (long long)lda, (long long)k);
+  // Stored shapes: A is m x k (k x m when transposed), B is k x n (n x k).
+  const int64_t a_rows = ta ? k : m, a_cols = ta ? m : k;
+  const int64_t b_rows = tb ? n : k, b_cols = tb ? k : n;
+  if (lda < a_cols) {
+    set_error("%s: lda=%lld < %s=%lld", what, (long long)lda, ta ? "m" : "k", (long long)a_cols);
     return MG_ERR_INVALID_ARG;
   }
-  if (ldb < n) {
-    set_error("%s: ldb=%lld < n=%lld", what, (long long)ldb, (long long)n);
+  if (ldb < b_cols) {
+    set_error("%s: ldb=%lld < %s=%lld", what, (long long)ldb, tb ? "k" : "n", (long long)b_cols);
     return MG_ERR_INVALID_ARG;
   }
   if (reinterpret_cast<uintptr_t>(A) % (uintptr_t)esz ||
@@ -79,12 +89,12 @@ int validate_problem(const char *what, int64_t m, int64_t n, int64_t k, double a
     set_error("%s: A or B not aligned to its element size", what);
     return MG_ERR_INVALID_ARG;
   }
-  if ((m - 1) > big / lda || (k - 1) > big / ldb) {
+  if ((a_rows - 1) > big / lda || (b_rows - 1) > big / ldb) {
     set_error("%s: A or B extent overflows", what);
     return MG_ERR_INVALID_ARG;
   }
-  if (spans_overlap(C, m, n, ldc, A, m, k, lda, esz) ||
-      spans_overlap(C, m, n, ldc, B, k, n, ldb, esz)) {
+  if (spans_overlap(C, m, n, ldc, A, a_rows, a_cols, lda, esz) ||
+      spans_overlap(C, m, n, ldc, B, b_rows, b_cols, ldb, esz)) {
     set_error("%s: C overlaps A or B", what);
     return MG_ERR_INVALID_ARG;
   }
@@ -209,6 +219,31 @@ int mg_gemm_cfg(int dtype, int cfg, int64_t m, int64_t n, int64_t k, double alph
   if (rc != MG_OK) return rc;
   return gemm_native(dtype, cfg, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
                      static_cast<hipStream_t>(stream));
+}
+
+int mg_gemm_ex(int dtype, int cfg, int transa, int transb, int64_t m, int64_t n, int64_t k,
+               double alpha, const void *A, int64_t lda, const void *B, int64_t ldb, double beta,
+               void *C, int64_t ldc, void *stream) {
+  clear_error();
+  const int64_t es = esize(dtype);
+  if (es == 0) {
+    set_error("unknown dtype %d", dtype);
+    return MG_ERR_INVALID_ARG;
+  }
+  if ((transa != 0 && transa != 1) || (transb != 0 && transb != 1)) {
+    set_error("transa/transb must be 0 or 1 (got %d, %d)", transa, transb);
+    return MG_ERR_INVALID_ARG;
+  }
+  if (cfg < -1 || cfg >= num_tile_cfgs()) {
+    set_error("unknown tile cfg %d", cfg);
+    return MG_ERR_INVALID_ARG;
+  }
+  int rc = validate_problem_op("gemm_ex", transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C,
+                               ldc, es);
+  if (rc != MG_OK) return rc;
+  if (cfg < 0) cfg = pick_tile_cfg(dtype, m, n, k);
+  return gemm_native_op(dtype, cfg, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                        static_cast<hipStream_t>(stream));
 }
 
 int mg_gemm(int dtype, int algo, int64_t m, int64_t n, int64_t k, double alpha, const void *A,

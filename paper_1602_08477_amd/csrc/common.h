@@ -85,4 +85,10 @@ int validate_problem(const char *what, int64_t m, int64_t n, int64_t k, double a
                      const void *A, int64_t lda, const void *B, int64_t ldb, double beta,
                      const void *C, int64_t ldc, int64_t esz);
 
+// Same for C <- alpha*op(A)*op(B) + beta*C: A stored k x m when ta, B stored
+// n x k when tb.
+int validate_problem_op(const char *what, bool ta, bool tb, int64_t m, int64_t n, int64_t k,
+                        double alpha, const void *A, int64_t lda, const void *B, int64_t ldb,
+                        double beta, const void *C, int64_t ldc, int64_t esz);
+
 }  // namespace mg

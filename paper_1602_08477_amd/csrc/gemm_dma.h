@@ -18,6 +18,10 @@
 //   B [128/size rows of k][BN*size B], row-major like B in HBM, chunks XOR-
 //     swizzled per k row so the four lane groups' rows of one fragment read
 //     fall on different banks.
+// Transposed operands keep the stored rows intact: A^T (stored k x m) lands
+// as [k rows][BM*size B] with B's swizzle and is read one value per MFMA like
+// B; B^T (stored n x k) lands as [BN rows][128 B] with A's swizzle and is read
+// one 16-byte chunk per VEC MFMAs like A.  Stage sizes are the same.
 #pragma once
 
 #include "gemm_tile.h"
@@ -33,6 +37,8 @@ struct DmaShape {
   static constexpr int BK = 128 / ESZ;
   static constexpr int RB = BN * ESZ;          // B row bytes in LDS
   static constexpr int CPB = RB / 16;          // 16-byte chunks per B row
+  static constexpr int RA = BM * ESZ;          // row bytes of a transposed A stage
+  static constexpr int CPA = RA / 16;
   static constexpr int A_BYTES = BM * 128;
   static constexpr int STAGE = A_BYTES + 128 * BN;  // B block: BK rows of RB bytes
   static constexpr size_t LDS_BYTES = (size_t)NS * STAGE;
@@ -86,7 +92,7 @@ __device__ __forceinline__ void dma_wait_steps(int q) {
   else dma_wait_vmcnt<3 * DPS>();
 }
 
-template <typename T, int BM, int BN, int WGM, int WGN, int NS>
+template <typename T, int BM, int BN, int WGM, int WGN, int NS, bool TA = false, bool TB = false>
 __device__ __forceinline__ void gemm_dma_tile(const GemmArgs<T> &g, int m0, int n0,
                                               unsigned char *lds) {
   typedef DmaShape<T, BM, BN, WGM, WGN, NS> S;
@@ -95,6 +101,9 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs<T> &g, int m0, int 
   typedef typename M::acc_t Acc;
   constexpr int ESZ = S::ESZ, VEC = S::VEC, BK = S::BK;
   constexpr int DPS = S::IA + S::IB;  // DMA instructions per k-step per wave
+  static_assert(!TA || (S::CPA >= 8 && (S::CPA & (S::CPA - 1)) == 0),
+                "transposed A rows of 2^j >= 8 chunks");
+  static_assert(ESZ == 4 || (S::CPB >= 16 && (!TA || S::CPA >= 16)), "FP64 swizzle flips bit 3");
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -103,36 +112,65 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs<T> &g, int m0, int 
   const int gq = lane >> 4, l16 = lane & 15;
 
   // Source of this lane's chunk in every DMA slot, without the k-step offset.
-  // A slot u: rows 8q .. 8q+7 (q = wave*IA + u), lane -> row 8q + lane/8,
-  // physical chunk lane%8 holding logical chunk c.  B slot u: LDS bytes
-  // [1024q, 1024q + 1024) of the B block.  Rows past m and chunks past n are
-  // clamped to the last valid ones.
+  // Rows of 128 B of k (A, or stored B^T): slot u covers rows 8q .. 8q+7
+  // (q = wave*I + u), lane -> row 8q + lane/8, physical chunk lane%8 holding
+  // logical chunk c; koff = c*VEC.  Rows of k (B, or stored A^T): slot u
+  // covers stage bytes [1024q, 1024q + 1024); koff = the k row.  Rows past
+  // the matrix and chunks past its columns are clamped to the last valid ones.
   const char *A = reinterpret_cast<const char *>(g.A);
   const char *B = reinterpret_cast<const char *>(g.B);
-  const int last_col_chunk = ((g.n - 1) / VEC) * VEC;
   const char *asrc[S::IA];
   int akofs[S::IA];
 #pragma unroll
   for (int u = 0; u < S::IA; ++u) {
-    const int row = 8 * (wave * S::IA + u) + (lane >> 3);
-    akofs[u] = dma_swz_a(row, lane & 7) * VEC;
-    const int gr = min(m0 + row, g.m - 1);
-    asrc[u] = A + ((int64_t)gr * g.lda + akofs[u]) * ESZ;
+    if constexpr (!TA) {
+      const int row = 8 * (wave * S::IA + u) + (lane >> 3);
+      akofs[u] = dma_swz_a(row, lane & 7) * VEC;
+      const int gr = min(m0 + row, g.m - 1);
+      asrc[u] = A + ((int64_t)gr * g.lda + akofs[u]) * ESZ;
+    } else {
+      const int o = (wave * S::IA + u) * 1024 + lane * 16;
+      const int row = o / S::RA;
+      const int c = dma_swz_b<T, S::CPA>(row, (o % S::RA) >> 4);
+      akofs[u] = row;
+      const int gc = min(m0 + c * VEC, ((g.m - 1) / VEC) * VEC);
+      asrc[u] = A + ((int64_t)row * g.lda + gc) * ESZ;
+    }
   }
   const char *bsrc[S::IB];
   int bkrow[S::IB];
 #pragma unroll
   for (int u = 0; u < S::IB; ++u) {
-    const int o = (wave * S::IB + u) * 1024 + lane * 16;
-    const int row = o / S::RB;
-    const int c = dma_swz_b<T, S::CPB>(row, (o % S::RB) >> 4);
-    bkrow[u] = row;
-    const int gc = min(n0 + c * VEC, last_col_chunk);
-    bsrc[u] = B + ((int64_t)row * g.ldb + gc) * ESZ;
+    if constexpr (!TB) {
+      const int o = (wave * S::IB + u) * 1024 + lane * 16;
+      const int row = o / S::RB;
+      const int c = dma_swz_b<T, S::CPB>(row, (o % S::RB) >> 4);
+      bkrow[u] = row;
+      const int gc = min(n0 + c * VEC, ((g.n - 1) / VEC) * VEC);
+      bsrc[u] = B + ((int64_t)row * g.ldb + gc) * ESZ;
+    } else {
+      const int row = 8 * (wave * S::IB + u) + (lane >> 3);
+      bkrow[u] = dma_swz_a(row, lane & 7) * VEC;
+      const int gr = min(n0 + row, g.n - 1);
+      bsrc[u] = B + ((int64_t)gr * g.ldb + bkrow[u]) * ESZ;
+    }
   }
 
   const int KT = (g.k + BK - 1) / BK;
   const int last_k_chunk = ((g.k - 1) / VEC) * VEC;
+  // k-step offset of a slot: along the row (k-contiguous rows) or down the
+  // rows (k rows); on the partial last step the k chunk / k row is clamped.
+  auto src_k = [&](const char *src, int koff, int64_t ld, bool krows, int kbase,
+                   bool tail) -> const char * {
+    if (!krows) {
+      if (!tail) return src + (int64_t)kbase * ESZ;
+      const int kk = min(kbase + koff, last_k_chunk);
+      return src + (int64_t)(kk - koff) * ESZ;
+    }
+    if (!tail) return src + (int64_t)kbase * ld * ESZ;
+    const int kr = min(kbase + koff, g.k - 1);
+    return src + (int64_t)(kr - koff) * ld * ESZ;
+  };
   auto issue = [&](int kt) {
     const int kbase = kt * BK;
     unsigned char *la = lds + (kt % NS) * S::STAGE;
@@ -140,22 +178,21 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs<T> &g, int m0, int 
     if (kbase + BK <= g.k) {
 #pragma unroll
       for (int u = 0; u < S::IA; ++u)
-        dma_lds16(asrc[u] + (int64_t)kbase * ESZ, la + (wave * S::IA + u) * 1024);
-      const int64_t bstep = (int64_t)kbase * g.ldb * ESZ;
+        dma_lds16(src_k(asrc[u], akofs[u], g.lda, TA, kbase, false),
+                  la + (wave * S::IA + u) * 1024);
 #pragma unroll
-      for (int u = 0; u < S::IB; ++u) dma_lds16(bsrc[u] + bstep, lb + (wave * S::IB + u) * 1024);
-    } else {  // partial last step: clamp k to the last valid chunk / row
-#pragma unroll
-      for (int u = 0; u < S::IA; ++u) {
-        const int kk = min(kbase + akofs[u], last_k_chunk);
-        dma_lds16(asrc[u] + (int64_t)(kk - akofs[u]) * ESZ, la + (wave * S::IA + u) * 1024);
-      }
-#pragma unroll
-      for (int u = 0; u < S::IB; ++u) {
-        const int kr = min(kbase + bkrow[u], g.k - 1);
-        dma_lds16(bsrc[u] + (int64_t)(kr - bkrow[u]) * g.ldb * ESZ,
+      for (int u = 0; u < S::IB; ++u)
+        dma_lds16(src_k(bsrc[u], bkrow[u], g.ldb, !TB, kbase, false),
                   lb + (wave * S::IB + u) * 1024);
-      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < S::IA; ++u)
+        dma_lds16(src_k(asrc[u], akofs[u], g.lda, TA, kbase, true),
+                  la + (wave * S::IA + u) * 1024);
+#pragma unroll
+      for (int u = 0; u < S::IB; ++u)
+        dma_lds16(src_k(bsrc[u], bkrow[u], g.ldb, !TB, kbase, true),
+                  lb + (wave * S::IB + u) * 1024);
     }
   };
 
@@ -173,7 +210,25 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs<T> &g, int m0, int 
 #pragma unroll
       for (int i = 0; i < S::FM; ++i) {
         const int row = wm0 + 16 * i + l16;
-        a[i] = *reinterpret_cast<const V *>(As + row * 128 + dma_swz_a(row, kc) * 16);
+        if constexpr (!TA) {
+          a[i] = *reinterpret_cast<const V *>(As + row * 128 + dma_swz_a(row, kc) * 16);
+        } else {
+          const int byte = row * ESZ;
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) {
+            const int kr = kc * VEC + v;
+            a[i][v] = *reinterpret_cast<const T *>(
+                As + kr * S::RA + dma_swz_b<T, S::CPA>(kr, byte >> 4) * 16 + (byte & 15));
+          }
+        }
+      }
+      V bv[S::FN];  // transposed B: one chunk of VEC k values per block column
+      if constexpr (TB) {
+#pragma unroll
+        for (int j = 0; j < S::FN; ++j) {
+          const int col = wn0 + 16 * j + l16;
+          bv[j] = *reinterpret_cast<const V *>(Bs + col * 128 + dma_swz_a(col, kc) * 16);
+        }
       }
 #pragma unroll
       for (int v = 0; v < VEC; ++v) {
@@ -181,10 +236,14 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs<T> &g, int m0, int 
         T b[S::FN];
 #pragma unroll
         for (int j = 0; j < S::FN; ++j) {
-          const int byte = (wn0 + 16 * j + l16) * ESZ;
-          b[j] = *reinterpret_cast<const T *>(Bs + kr * S::RB +
-                                              dma_swz_b<T, S::CPB>(kr, byte >> 4) * 16 +
-                                              (byte & 15));
+          if constexpr (!TB) {
+            const int byte = (wn0 + 16 * j + l16) * ESZ;
+            b[j] = *reinterpret_cast<const T *>(Bs + kr * S::RB +
+                                                dma_swz_b<T, S::CPB>(kr, byte >> 4) * 16 +
+                                                (byte & 15));
+          } else {
+            b[j] = bv[j][v];
+          }
         }
 #pragma unroll
         for (int i = 0; i < S::FM; ++i)
@@ -197,19 +256,25 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs<T> &g, int m0, int 
   // Last, partial k-step: zero every k >= kvalid of the landed stage (A
   // columns, B rows), so values read from clamped addresses never reach the
   // sums; the same zeros the register-staged tile loads past k.
-  auto zero_tail = [&](unsigned char *As, unsigned char *Bs, int kvalid) {
-    for (int e = tid; e < BM * 8; e += S::THREADS) {
+  auto zero_krows = [&](unsigned char *X, int cp, int kvalid) {  // [k rows][cp chunks]
+    for (int e = tid; e < BK * cp; e += S::THREADS)
+      if (e / cp >= kvalid) *reinterpret_cast<V *>(X + e * 16) = V{};
+  };
+  auto zero_kcols = [&](unsigned char *X, int rows, int kvalid) {  // [rows][128 B of k]
+    for (int e = tid; e < rows * 8; e += S::THREADS) {
       const int row = e >> 3, c = e & 7;
       if ((c + 1) * VEC <= kvalid) continue;
-      T *p = reinterpret_cast<T *>(As + row * 128 + dma_swz_a(row, c) * 16);
+      T *p = reinterpret_cast<T *>(X + row * 128 + dma_swz_a(row, c) * 16);
 #pragma unroll
       for (int v = 0; v < VEC; ++v)
         if (c * VEC + v >= kvalid) p[v] = T(0);
     }
-    for (int e = tid; e < BK * S::CPB; e += S::THREADS) {
-      const int kr = e / S::CPB;
-      if (kr >= kvalid) *reinterpret_cast<V *>(Bs + e * 16) = V{};
-    }
+  };
+  auto zero_tail = [&](unsigned char *As, unsigned char *Bs, int kvalid) {
+    if constexpr (!TA) zero_kcols(As, BM, kvalid);
+    else zero_krows(As, S::CPA, kvalid);
+    if constexpr (!TB) zero_krows(Bs, S::CPB, kvalid);
+    else zero_kcols(Bs, BN, kvalid);
   };
 
 #pragma unroll

@@ -17,8 +17,14 @@
 //      row form one 16-byte chunk, written as loaded from row-major A and read
 //      back with one ds_read_b128 that feeds VEC MFMAs.
 //   B: [BK][BN+PB]          -- row-major like B in HBM.
+// Transposed operands (op(A) = A^T with A stored k x m, op(B) = B^T with B
+// stored n x k) swap layouts: a stored row of A^T is a k row of the tile, so
+// it is staged like B ([BK][BM+PB], read one value per MFMA), and a stored
+// row of B^T runs along k, so it is staged like A ([BK/VEC][BN+PA][VEC], read
+// one 16-byte chunk per VEC MFMAs).
 // Fragment k mapping: lane group g = lane/16 supplies k = VEC*(4r+g)+v to the
-// v-th MFMA of round r on both operands, so A and B always agree on k.
+// v-th MFMA of round r on both operands, so A and B always agree on k, and
+// every output sums its products in the same order for every layout.
 #pragma once
 
 #include "common.h"
@@ -69,7 +75,8 @@ constexpr int kTileThreads = 256;
 
 // Macro-tile BM x BN computed by WGM x WGN wavefronts (each a WM x WN wave
 // tile of 16x16 MFMA blocks), k-step BK = BKM times the type's base step.
-template <typename T, int BM, int BN, int WGM = 2, int WGN = 2, int BKM = 1>
+template <typename T, int BM, int BN, int WGM = 2, int WGN = 2, int BKM = 1, bool TA = false,
+          bool TB = false>
 struct TileShape {
   typedef Mfma<T> M;
   static constexpr int THREADS = 64 * WGM * WGN;
@@ -87,8 +94,8 @@ struct TileShape {
   static constexpr int B_CHUNKS = BK * BN / VEC;
   static constexpr int NA = A_CHUNKS / THREADS;  // per thread
   static constexpr int NB = B_CHUNKS / THREADS;
-  static constexpr int A_STAGE = ACH * (BM + PA) * VEC;  // elements
-  static constexpr int B_STAGE = BK * (BN + PB);
+  static constexpr int A_STAGE = TA ? BK * (BM + PB) : ACH * (BM + PA) * VEC;  // elements
+  static constexpr int B_STAGE = TB ? ACH * (BN + PA) * VEC : BK * (BN + PB);
   static constexpr int STAGE = A_STAGE + B_STAGE;
   static constexpr size_t LDS_BYTES = 2 * STAGE * sizeof(T);
   static_assert(WM % 16 == 0 && WN % 16 == 0 && FM >= 1 && FN >= 1, "wave tile of 16x16 blocks");
@@ -226,18 +233,21 @@ struct Epilogue<float, VEC_OK> {
   }
 };
 
-// Computes the BM x BN tile of C whose top-left output is (m0, n0).
+// Computes the BM x BN tile of C whose top-left output is (m0, n0) of
+// C <- alpha*op(A)*op(B) + beta*C (op = transpose when TA / TB is set).
 // `smem` holds 2 stages of TileShape::STAGE elements.  All THREADS lanes of
 // the workgroup must call this together (it contains barriers).
-template <typename T, int BM, int BN, bool VEC_OK, int WGM = 2, int WGN = 2, int BKM = 1>
+template <typename T, int BM, int BN, bool VEC_OK, int WGM = 2, int WGN = 2, int BKM = 1,
+          bool TA = false, bool TB = false>
 __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &g, int m0, int n0, T *smem) {
-  typedef TileShape<T, BM, BN, WGM, WGN, BKM> S;
+  typedef TileShape<T, BM, BN, WGM, WGN, BKM, TA, TB> S;
   typedef Mfma<T> M;
   typedef typename M::vec_t V;
   typedef typename M::acc_t Acc;
   constexpr int VEC = S::VEC, BK = S::BK;
-  constexpr int ACH = S::ACH;    // A chunks per tile row
-  constexpr int BCH = BN / VEC;  // B chunks per tile row
+  constexpr int ACH = S::ACH;    // k chunks per tile row of A (and of stored B^T)
+  constexpr int BCH = BN / VEC;  // n chunks per k row of B
+  constexpr int MCH = BM / VEC;  // m chunks per k row of stored A^T
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -245,30 +255,49 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &g, int m0, int n0, 
   const int gq = lane >> 4, l16 = lane & 15;
 
   // Per-thread global chunk coordinates (fixed across k-tiles).
+  // A: (a_i, a_j) = (tile row, k chunk); transposed: (k row, first m column).
   const T *pa[S::NA];
   bool a_ok[S::NA];
-  int a_kc[S::NA], a_row[S::NA];
+  int a_i[S::NA], a_j[S::NA], a_left[S::NA];
 #pragma unroll
   for (int u = 0; u < S::NA; ++u) {
     const int q = tid + S::THREADS * u;
-    a_row[u] = q / ACH;
-    a_kc[u] = q % ACH;
-    const int grow = m0 + a_row[u];
-    a_ok[u] = grow < g.m;
-    pa[u] = g.A + (int64_t)(a_ok[u] ? grow : 0) * g.lda + a_kc[u] * VEC;
+    if constexpr (!TA) {
+      a_i[u] = q / ACH;
+      a_j[u] = q % ACH;
+      const int grow = m0 + a_i[u];
+      a_ok[u] = grow < g.m;
+      pa[u] = g.A + (int64_t)(a_ok[u] ? grow : 0) * g.lda + a_j[u] * VEC;
+    } else {
+      a_i[u] = q / MCH;
+      a_j[u] = (q % MCH) * VEC;
+      const int gcol = m0 + a_j[u];
+      a_ok[u] = gcol < g.m;
+      a_left[u] = g.m - gcol;
+      pa[u] = g.A + (int64_t)a_i[u] * g.lda + (a_ok[u] ? gcol : 0);
+    }
   }
+  // B: (b_i, b_j) = (k row, first n column); transposed: (tile column, k chunk).
   const T *pb[S::NB];
   bool b_ok[S::NB];
-  int b_r[S::NB], b_c[S::NB], b_left[S::NB];
+  int b_i[S::NB], b_j[S::NB], b_left[S::NB];
 #pragma unroll
   for (int u = 0; u < S::NB; ++u) {
     const int q = tid + S::THREADS * u;
-    b_r[u] = q / BCH;
-    b_c[u] = (q % BCH) * VEC;
-    const int gcol = n0 + b_c[u];
-    b_ok[u] = gcol < g.n;
-    b_left[u] = g.n - gcol;
-    pb[u] = g.B + (int64_t)b_r[u] * g.ldb + (b_ok[u] ? gcol : 0);
+    if constexpr (!TB) {
+      b_i[u] = q / BCH;
+      b_j[u] = (q % BCH) * VEC;
+      const int gcol = n0 + b_j[u];
+      b_ok[u] = gcol < g.n;
+      b_left[u] = g.n - gcol;
+      pb[u] = g.B + (int64_t)b_i[u] * g.ldb + (b_ok[u] ? gcol : 0);
+    } else {
+      b_i[u] = q / ACH;
+      b_j[u] = q % ACH;
+      const int gcol = n0 + b_i[u];
+      b_ok[u] = gcol < g.n;
+      pb[u] = g.B + (int64_t)(b_ok[u] ? gcol : 0) * g.ldb + b_j[u] * VEC;
+    }
   }
 
   V ra[S::NA], rb[S::NB];
@@ -276,25 +305,44 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &g, int m0, int n0, 
     const int kbase = kt * BK;
 #pragma unroll
     for (int u = 0; u < S::NA; ++u) {
-      const int kk = kbase + a_kc[u] * VEC;
-      ra[u] = load_chunk<T, VEC_OK>(pa[u] + kbase, a_ok[u], g.k - kk);
+      if constexpr (!TA) {
+        const int kk = kbase + a_j[u] * VEC;
+        ra[u] = load_chunk<T, VEC_OK>(pa[u] + kbase, a_ok[u], g.k - kk);
+      } else {
+        const int kr = kbase + a_i[u];
+        ra[u] = load_chunk<T, VEC_OK>(pa[u] + (int64_t)kbase * g.lda, a_ok[u] && kr < g.k,
+                                      a_left[u]);
+      }
     }
 #pragma unroll
     for (int u = 0; u < S::NB; ++u) {
-      const int kr = kbase + b_r[u];
-      rb[u] = load_chunk<T, VEC_OK>(pb[u] + (int64_t)kbase * g.ldb, b_ok[u] && kr < g.k,
-                                    b_left[u]);
+      if constexpr (!TB) {
+        const int kr = kbase + b_i[u];
+        rb[u] = load_chunk<T, VEC_OK>(pb[u] + (int64_t)kbase * g.ldb, b_ok[u] && kr < g.k,
+                                      b_left[u]);
+      } else {
+        const int kk = kbase + b_j[u] * VEC;
+        rb[u] = load_chunk<T, VEC_OK>(pb[u] + kbase, b_ok[u], g.k - kk);
+      }
     }
   };
   auto store_tiles = [&](int stage) {
     T *As = smem + stage * S::STAGE;
     T *Bs = As + S::A_STAGE;
 #pragma unroll
-    for (int u = 0; u < S::NA; ++u)
-      *reinterpret_cast<V *>(As + (a_kc[u] * (BM + S::PA) + a_row[u]) * VEC) = ra[u];
+    for (int u = 0; u < S::NA; ++u) {
+      if constexpr (!TA)
+        *reinterpret_cast<V *>(As + (a_j[u] * (BM + S::PA) + a_i[u]) * VEC) = ra[u];
+      else
+        *reinterpret_cast<V *>(As + a_i[u] * (BM + S::PB) + a_j[u]) = ra[u];
+    }
 #pragma unroll
-    for (int u = 0; u < S::NB; ++u)
-      *reinterpret_cast<V *>(Bs + b_r[u] * (BN + S::PB) + b_c[u]) = rb[u];
+    for (int u = 0; u < S::NB; ++u) {
+      if constexpr (!TB)
+        *reinterpret_cast<V *>(Bs + b_i[u] * (BN + S::PB) + b_j[u]) = rb[u];
+      else
+        *reinterpret_cast<V *>(Bs + (b_j[u] * (BN + S::PA) + b_i[u]) * VEC) = rb[u];
+    }
   };
 
   Acc acc[S::FM][S::FN];
@@ -319,13 +367,31 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &g, int m0, int n0, 
       const int kc = 4 * r + gq;  // this lane group's chunk
       V a[S::FM];
 #pragma unroll
-      for (int i = 0; i < S::FM; ++i)
-        a[i] = *reinterpret_cast<const V *>(As + (kc * (BM + S::PA) + wm0 + 16 * i + l16) * VEC);
+      for (int i = 0; i < S::FM; ++i) {
+        if constexpr (!TA) {
+          a[i] = *reinterpret_cast<const V *>(As + (kc * (BM + S::PA) + wm0 + 16 * i + l16) * VEC);
+        } else {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v)
+            a[i][v] = As[(kc * VEC + v) * (BM + S::PB) + wm0 + 16 * i + l16];
+        }
+      }
+      V bv[S::FN];  // transposed B: one chunk of VEC k values per block column
+      if constexpr (TB) {
+#pragma unroll
+        for (int j = 0; j < S::FN; ++j)
+          bv[j] = *reinterpret_cast<const V *>(Bs + (kc * (BN + S::PA) + wn0 + 16 * j + l16) * VEC);
+      }
 #pragma unroll
       for (int v = 0; v < VEC; ++v) {
         T b[S::FN];
 #pragma unroll
-        for (int j = 0; j < S::FN; ++j) b[j] = Bs[(kc * VEC + v) * (BN + S::PB) + wn0 + 16 * j + l16];
+        for (int j = 0; j < S::FN; ++j) {
+          if constexpr (!TB)
+            b[j] = Bs[(kc * VEC + v) * (BN + S::PB) + wn0 + 16 * j + l16];
+          else
+            b[j] = bv[j][v];
+        }
 #pragma unroll
         for (int i = 0; i < S::FM; ++i)
 #pragma unroll

@@ -41,7 +41,7 @@ template <typename T>
 struct GTileRec {
   GemmArgs<T> g;
   int tm, tn;
-  int cls;  // class | (A, B, C 16-byte rows << 4) | (C 16-byte rows << 5)
+  int cls;  // class | (C rows 16-byte aligned << 4)
   int pad;
 };
 
@@ -56,54 +56,10 @@ __device__ __forceinline__ void scale_tile(const GemmArgs<T> &g, int m0, int n0)
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void run_tile(const GTileRec<T> &t, T *smem) {
-  const bool vec = (t.cls >> 4) & 1;
-  switch (t.cls & 15) {
-    case 0:
-      if (vec) gemm_tile<T, 64, 64, true>(t.g, t.tm * 64, t.tn * 64, smem);
-      else gemm_tile<T, 64, 64, false>(t.g, t.tm * 64, t.tn * 64, smem);
-      break;
-    case 1:
-      if (vec) gemm_tile<T, 64, 32, true>(t.g, t.tm * 64, t.tn * 32, smem);
-      else gemm_tile<T, 64, 32, false>(t.g, t.tm * 64, t.tn * 32, smem);
-      break;
-    case 2:
-      if (vec) gemm_tile<T, 32, 32, true>(t.g, t.tm * 32, t.tn * 32, smem);
-      else gemm_tile<T, 32, 32, false>(t.g, t.tm * 32, t.tn * 32, smem);
-      break;
-    default:
-      scale_tile<T>(t.g, t.tm * kScaleTile, t.tn * kScaleTile);
-      break;
-  }
-}
-
-// Persistent loop over tiles blockIdx.x, +gridDim.x, ...; the next record is
-// loaded (uniform, scalar loads) before the current tile is computed.
-template <typename T>
-__global__ __launch_bounds__(kTileThreads, 3) void grouped_kernel(
-    const GTileRec<T> *__restrict__ tiles, int ntiles) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  T *smem = reinterpret_cast<T *>(lds_raw);
-  int w = blockIdx.x;
-  if (w >= ntiles) return;
-  GTileRec<T> cur = tiles[w];
-  for (;;) {
-    const int nw = w + (int)gridDim.x;
-    GTileRec<T> nxt = cur;
-    if (nw < ntiles) nxt = tiles[nw];
-    run_tile<T>(cur, smem);
-    if (nw >= ntiles) break;
-    __syncthreads();  // LDS of this tile fully consumed before the next one
-    w = nw;
-    cur = nxt;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Persistent kernel with a ring of direct global->LDS loads.
 //
-// Each workgroup walks its tiles (b, b+G, ...) as one stream of k-steps.  A
+// Each workgroup walks its dealt tiles as one stream of k-steps.  A
 // load cursor runs NS-1 steps ahead of the compute cursor and fills an
 // NS-stage LDS ring with global_load_lds (4 bytes per lane, so any leading
 // dimension and any element alignment is accepted), across tile boundaries:
@@ -285,7 +241,7 @@ __device__ __forceinline__ void gd_store(const GTileRec<T> &t,
                                          int wave, int lane) {
   constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
   const int m0 = t.tm * BM + (wave >> 1) * WM, n0 = t.tn * BN + (wave & 1) * WN;
-  if ((t.cls >> 5) & 1) Epilogue<T, true>::template store<FM, FN>(t.g, acc, m0, n0, lane);
+  if ((t.cls >> 4) & 1) Epilogue<T, true>::template store<FM, FN>(t.g, acc, m0, n0, lane);
   else Epilogue<T, false>::template store<FM, FN>(t.g, acc, m0, n0, lane);
 }
 
@@ -507,16 +463,12 @@ int build_t(int64_t count, const mg_problem *probs, const mg_tune_table *table, 
     }
     int cls = table ? table->cls[tune_bucket(q.m, q.n, q.k)] : heuristic_class(q.m, q.n);
     if (cls < 0 || cls >= kNumGroupedClasses) cls = heuristic_class(q.m, q.n);
-    constexpr int VEC = Mfma<T>::VEC;
-    const bool vec = vec_aligned(q.A, q.lda, sizeof(T), VEC) &&
-                     vec_aligned(q.B, q.ldb, sizeof(T), VEC) &&
-                     vec_aligned(q.C, q.ldc, sizeof(T), VEC);
-    const bool c_vec = vec_aligned(q.C, q.ldc, sizeof(T), VEC);
+    const bool c_vec = vec_aligned(q.C, q.ldc, sizeof(T), Mfma<T>::VEC);
     const int bm = kClsBM[cls], bn = kClsBN[cls];
     const int tm = (int)ceil_div(q.m, bm), tn = (int)ceil_div(q.n, bn);
     for (int a = 0; a < tm; ++a)
       for (int b = 0; b < tn; ++b) {
-        tiles.push_back(GTileRec<T>{g, a, b, cls | (vec ? 16 : 0) | (c_vec ? 32 : 0), 0});
+        tiles.push_back(GTileRec<T>{g, a, b, cls | (c_vec ? 16 : 0), 0});
         // MFMA work of the padded tile plus its operand traffic (in FLOP-equivalents)
         cost.push_back(2.0 * bm * bn * (double)round_up(q.k, Mfma<T>::BK) +
                        16.0 * (bm + bn) * (double)q.k);

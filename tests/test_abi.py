@@ -122,3 +122,40 @@ def test_split_layout_and_errors():
     rc = lib.mg_gemm_split(mg.SPLIT_I8, 7, 8, 8, 8, 1.0, FAKE, 8, FAKE_B, 8, 0.0, FAKE_C, 8,
                            FAKE_C, 1 << 20, NULL)
     assert rc == mg.ERR_INVALID_ARG
+
+
+def call_gemm_ex(dt=mg.F64, cfg=-1, ta=0, tb=0, m=8, n=6, k=4, A=FAKE, lda=None, B=FAKE_B,
+                 ldb=None, C=FAKE_C, ldc=6, alpha=1.0, beta=0.0):
+    lda = (m if ta else k) if lda is None else lda
+    ldb = (k if tb else n) if ldb is None else ldb
+    return mg.lib().mg_gemm_ex(dt, cfg, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                               NULL)
+
+
+@pytest.mark.parametrize("kw,code,needle", [
+    (dict(ta=2), mg.ERR_INVALID_ARG, "trans"),
+    (dict(tb=-1), mg.ERR_INVALID_ARG, "trans"),
+    (dict(cfg=-2), mg.ERR_INVALID_ARG, "cfg"),
+    (dict(cfg=NATIVE_CFGS), mg.ERR_INVALID_ARG, "cfg"),
+    (dict(dt=5), mg.ERR_INVALID_ARG, "dtype"),
+    # stored A^T is k x m: its pitch must cover m, not k
+    (dict(ta=1, lda=4), mg.ERR_INVALID_ARG, "lda"),
+    (dict(ta=0, lda=3), mg.ERR_INVALID_ARG, "lda"),
+    # stored B^T is n x k: its pitch must cover k, not n
+    (dict(tb=1, ldb=3), mg.ERR_INVALID_ARG, "ldb"),
+    (dict(tb=0, ldb=5), mg.ERR_INVALID_ARG, "ldb"),
+    # C placed inside the stored extent of A^T (k rows of pitch m: 32 doubles)
+    (dict(ta=1, C=ctypes.c_void_p(0x10000000 + 8 * 30)), mg.ERR_INVALID_ARG, "overlap"),
+    # C inside the stored extent of B^T (n rows of pitch k: 24 doubles)
+    (dict(tb=1, C=ctypes.c_void_p(0x20000000 + 8 * 20)), mg.ERR_INVALID_ARG, "overlap"),
+    (dict(ta=1, A=NULL), mg.ERR_INVALID_ARG, "NULL"),
+])
+def test_gemm_ex_invalid_arguments(kw, code, needle):
+    assert call_gemm_ex(**kw) == code
+    assert needle in mg.last_error()
+
+
+def test_gemm_ex_empty_problem_is_ok_without_gpu():
+    assert call_gemm_ex(m=0, ta=1, lda=1) == mg.OK
+    assert call_gemm_ex(n=0, tb=1, C=NULL) == mg.OK
+    assert mg.last_error() == ""

@@ -256,6 +256,72 @@ def bench_trans(n, steps, warmup):
     return {"m": n, "n": n, "k": n, "tile_cfg": mg.pick_tile_cfg(n, n, n), "layouts": out}
 
 
+def bench_daxpy(n, steps, warmup, cpu=True, small_n=True):
+    """DAXPY y <- 1.5 x + y (Section 4.1) on U[-1,1) vectors of n doubles:
+    kernel time from HIP events on the launch stream, 24 bytes per element
+    (x and y read, y written) against the 8 TB/s HBM peak; a plain 1 GiB
+    device copy timed the same way for the bandwidth this part reaches; the
+    library's per-call cost at tiny n (host wall time per call over 2000
+    back-to-back calls vs the kernel's event time); every element of one
+    launch checked against the oracle; the oracle's own rate on the host."""
+    import torch
+    import paper_1602_08477_amd as mg
+    import oracle
+    import synth
+    seed = synth.config_seed(3)
+    stream = torch.cuda.current_stream()
+    dx = synth.uniform_pm1(seed, 0, n, device="cuda")
+    dy = synth.uniform_pm1(seed, 1, n, device="cuda")
+    x_h, y_h = dx.cpu().numpy(), dy.cpu().numpy()
+    per, _ = time_launches(lambda: mg.daxpy(1.5, dx, dy), max(steps, 20), warmup, stream)
+    ms = float(np.mean(per))
+    alg_bytes = 24.0 * n
+    gbs = alg_bytes / ms / 1e6
+    # parity of one launch on fresh inputs
+    dy.copy_(torch.from_numpy(y_h))
+    mg.daxpy(1.5, dx, dy)
+    torch.cuda.synchronize()
+    exact = bool(np.array_equal(dy.cpu().numpy(), oracle.daxpy(1.5, x_h, y_h)))
+    # a plain device-to-device copy of 1 GiB (reads and writes 2 GiB)
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    per_c, _ = time_launches(lambda: dst.copy_(src), 20, 2, stream)
+    copy_gbs = 2.0 * src.numel() * 8 / float(np.mean(per_c)) / 1e6
+    del src, dst
+    # per-call cost at small n: host wall time per call vs kernel time
+    small = []
+    for m in ((1, 1024, 65536, 1 << 20) if small_n else ()):
+        sx, sy = dx[:m], dy[:m]
+        fn = lambda: mg.daxpy(1.5, sx, sy)  # noqa: E731
+        k_ms = float(np.median(time_launches(fn, 50, 5, stream)[0]))
+        torch.cuda.synchronize()
+        reps = 2000
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        wall_us = (time.perf_counter() - t0) * 1e6 / reps
+        small.append({"n": m, "kernel_us": round(k_ms * 1e3, 2),
+                      "wall_us_per_call": round(wall_us, 2)})
+    rec = {"n": n, "alpha": 1.5, "ms": round(ms, 4), "gb_per_s": round(gbs, 1),
+           "bit_exact_vs_oracle": exact,
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0,
+                        "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
+                        "alg_bytes_per_launch": alg_bytes, "kernel_ms": round(ms, 4)},
+           "context_device_copy_gb_per_s": round(copy_gbs, 1),
+           "small_n": small}
+    if cpu:
+        oracle.daxpy(1.5, x_h[:1 << 20], y_h[:1 << 20])  # first touch of the pages, threads up
+        t0 = time.perf_counter()
+        oracle.daxpy(1.5, x_h, y_h)
+        t = time.perf_counter() - t0
+        rec["cpu_oracle"] = {"gb_per_s": round(alg_bytes / t / 1e9, 2), "cores": oracle.threads(),
+                             "seconds": round(t, 3)}
+    del dx, dy
+    torch.cuda.empty_cache()
+    return rec
+
+
 def bench_split(n, steps, warmup):
     import torch
     import paper_1602_08477_amd as mg
@@ -480,7 +546,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--quick", action="store_true", help="headline only (for profiling)")
-    ap.add_argument("--leg", choices=["sizes", "trans", "split", "batched", "serving"],
+    ap.add_argument("--leg", choices=["sizes", "trans", "daxpy", "split", "batched", "serving"],
                     default=None,
                     help="run only this secondary leg and print its record (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -504,6 +570,8 @@ def main():
         fn = {"split": lambda: bench_split(4096, max(3, args.steps), 1),
               "sizes": lambda: bench_sizes(args.steps, args.warmup),
               "trans": lambda: bench_trans(args.n, args.steps, args.warmup),
+              "daxpy": lambda: bench_daxpy(1 << 27, args.steps, args.warmup,
+                                           cpu=not args.quick, small_n=not args.quick),
               "batched": lambda: bench_batched(max(3, args.steps)),
               "serving": lambda: bench_serving(args.serve_seconds)}[args.leg]
         print(json.dumps({"leg": args.leg, "record": fn()}), flush=True)
@@ -552,6 +620,8 @@ def main():
         rec["sizes"] = bench_sizes(args.steps, args.warmup)
         eprint("bench: operand layouts")
         rec["trans"] = bench_trans(n, args.steps, args.warmup)
+        eprint("bench: daxpy n=2^27")
+        rec["daxpy"] = bench_daxpy(1 << 27, args.steps, args.warmup)
         eprint("bench: split precision n=4096")
         rec["split"] = bench_split(4096, max(5, args.steps), 2)
         eprint("bench: batched 2000 problems")

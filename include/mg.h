@@ -111,6 +111,22 @@ int mg_gemm_ex(int dtype, int cfg, int transa, int transb, int64_t m, int64_t n,
                double alpha, const void *A, int64_t lda, const void *B, int64_t ldb, double beta,
                void *C, int64_t ldc, void *stream);
 
+/* ----------------------------------------------------------------- DAXPY --
+ * mg_daxpy: y <- alpha*x + y (the vector operation of the paper's conceptual
+ * comparison, Section 4.1).  Element i of x is x[i*incx], of y y[i*incy].
+ *   n          number of elements (>= 0).
+ *   incx, incy increments in elements, >= 1 (no reverse traversal).
+ *   x, y       DEVICE pointers to doubles (8-byte aligned), owned by the
+ *              caller; y may be x itself when incx == incy, no other overlap.
+ * Each element is one fused multiply-add: y[i] = alpha*x[i] + y[i] rounded
+ * once to the nearest double (ties to even), bit-identical for every launch
+ * shape.  BLAS quick return: n == 0 or alpha == 0 leaves y untouched and reads
+ * nothing (NaN in x does not propagate).  Asynchronous on `stream`.
+ * Returns MG_OK or MG_ERR_INVALID_ARG (negative n, increment < 1, NULL or
+ * misaligned pointer, overlap, extent overflow), MG_ERR_HIP on launch error. */
+int mg_daxpy(int64_t n, double alpha, const double *x, int64_t incx, double *y, int64_t incy,
+             void *stream);
+
 /* ------------------------------------------------ split-precision FP64 --
  * The FP64 product is rebuilt from exact integer slices (not part of the
  * paper, which computes DGEMM natively; the splitting follows Ozaki et al.'s

@@ -12,6 +12,8 @@ Contents
   exact_gemm(...)       exact rational evaluation (Python fractions) rounded
                         once to the nearest double; for tiny cases only.
   rel_fro_err(...)      ||X - R||_F / ||R||_F (absolute norm if R == 0).
+  daxpy(...)            y <- alpha x + y (Section 4.1), each element rounded
+                        once (C, fma); exact_axpy(...) the rational form.
   split_*(...)          the split-precision method written out plainly in
                         numpy (not part of the paper; the method is the
                         Ozaki-style error-free splitting described in the
@@ -51,6 +53,8 @@ def _load():
                                      ctypes.c_double, dp, i64]
         lib.oracle_dgemm.restype = ctypes.c_int
         lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_daxpy.argtypes = [i64, ctypes.c_double, dp, i64, dp, i64]
+        lib.oracle_daxpy.restype = ctypes.c_int
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
     return _lib
@@ -138,6 +142,33 @@ def exact_gemm(alpha, A, B, beta, C) -> np.ndarray:
                 v += be * Fraction(float(C[i, j]))
             out[i, j] = v.numerator / v.denominator
     return out
+
+
+def daxpy(alpha: float, x: np.ndarray, y: np.ndarray, n: int | None = None, incx: int = 1,
+          incy: int = 1) -> np.ndarray:
+    """DAXPY (Section 4.1): return a copy of the flat buffer ``y`` with
+    y[i*incy] <- alpha*x[i*incx] + y[i*incy] for i < n, each element the exact
+    value rounded once (see mg_oracle.c).  n defaults to the most elements the
+    buffers hold at these increments."""
+    x = np.ascontiguousarray(np.ravel(x), dtype=np.float64)
+    out = np.array(np.ravel(y), dtype=np.float64, copy=True)
+    if n is None:
+        n = min((x.size + incx - 1) // incx, (out.size + incy - 1) // incy)
+    if n > 0 and ((n - 1) * incx >= x.size or (n - 1) * incy >= out.size):
+        raise ValueError("buffers too short for n and the increments")
+    rc = _load().oracle_daxpy(int(n), float(alpha), _ptr(x), int(incx), _ptr(out), int(incy))
+    if rc != 0:
+        raise ValueError(f"oracle_daxpy rejected its arguments ({rc})")
+    return out
+
+
+def exact_axpy(alpha: float, x, y) -> np.ndarray:
+    """alpha*x[i] + y[i] evaluated exactly in rationals and rounded once to
+    the nearest double (Python's Fraction -> float conversion rounds
+    correctly, ties to even).  Finite inputs only; tiny cases."""
+    a = Fraction(alpha)
+    return np.array([float(a * Fraction(float(xi)) + Fraction(float(yi)))
+                     for xi, yi in zip(np.ravel(x), np.ravel(y))], dtype=np.float64)
 
 
 def rel_fro_err(X, R) -> float:

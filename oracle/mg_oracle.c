@@ -1,6 +1,7 @@
 /*
  * CPU oracle for the generalised matrix-matrix multiply C <- alpha*A*B + beta*C
- * (the DGEMM problem of Section 4.2, "Performance", of the Alpaka paper).
+ * (the DGEMM problem of Section 4.2, "Performance", of the Alpaka paper), and
+ * for DAXPY y <- alpha*x + y (Section 4.1), at the end of this file.
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or calls
  * this file; only the test suite, the smoke check and the bench's CPU-baseline
@@ -144,4 +145,25 @@ int oracle_dgemm(int64_t m, int64_t n, int64_t k, double alpha,
         free(c);
     }
     return failed ? -2 : 0;
+}
+
+/*
+ * DAXPY, the vector operation of the paper's conceptual comparison (Section
+ * 4.1): y <- alpha*x + y, element i of x at x[i*incx] and of y at y[i*incy].
+ * Each element is the exact value alpha*x[i] + y[i] rounded once to the
+ * nearest double (C99 fma, correctly rounded), the most accurate result a
+ * double can hold.  BLAS quick return: n == 0 or alpha == 0 leaves y as it is
+ * and reads nothing.  Returns 0, or -1 for negative n or increments below 1.
+ */
+int oracle_daxpy(int64_t n, double alpha, const double *x, int64_t incx, double *y,
+                 int64_t incy)
+{
+    if (n < 0 || incx < 1 || incy < 1)
+        return -1;
+    if (n == 0 || alpha == 0.0)
+        return 0;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        y[i * incy] = fma(alpha, x[i * incx], y[i * incy]);
+    return 0;
 }

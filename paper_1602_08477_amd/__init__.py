@@ -70,6 +70,7 @@ def lib() -> ctypes.CDLL:
         L.mg_gemm.argtypes = [_int, _int] + gemm_args
         L.mg_gemm_cfg.argtypes = [_int, _int] + gemm_args
         L.mg_gemm_ex.argtypes = [_int, _int, _int, _int] + gemm_args
+        L.mg_daxpy.argtypes = [_i64, _dbl, _vp, _i64, _vp, _i64, _vp]
         L.mg_split_default_slices.argtypes = [_int]
         L.mg_split_layout_query.argtypes = [_int, _int, _i64, _i64, _i64,
                                             ctypes.POINTER(SplitLayout)]
@@ -170,6 +171,23 @@ def gemm_ex(A, B, C, alpha: float = 1.0, beta: float = 0.0, transa: bool = False
     check(lib().mg_gemm_ex(_dtype_code(C), -1 if cfg is None else cfg, int(transa), int(transb),
                            m, n, k, alpha, pa, lda, pb, ldb, beta, pc, ldc, s))
     return C
+
+
+def daxpy(alpha: float, x, y, stream=None):
+    """y <- alpha*x + y in place (mg_daxpy).  x and y are 1-D float64 CUDA
+    tensors of equal length; their strides (>= 1) are the increments.
+    Returns y."""
+    for t, name in ((x, "x"), (y, "y")):
+        if t.dim() != 1:
+            raise ValueError(f"{name} must be 1-D")
+    if x.shape[0] != y.shape[0]:
+        raise ValueError("x and y lengths differ")
+    n = y.shape[0]
+    incx = x.stride(0) if n > 1 else 1
+    incy = y.stride(0) if n > 1 else 1
+    check(lib().mg_daxpy(n, alpha, ctypes.c_void_p(x.data_ptr()), incx,
+                         ctypes.c_void_p(y.data_ptr()), incy, _stream_handle(stream)))
+    return y
 
 
 def num_tile_cfgs() -> int:

@@ -7,6 +7,7 @@
 #include <utility>
 #include <vector>
 
+#include "axpy.h"
 #include "common.h"
 #include "gemm_native.h"
 #include "grouped.h"
@@ -244,6 +245,42 @@ int mg_gemm_ex(int dtype, int cfg, int transa, int transb, int64_t m, int64_t n,
   if (cfg < 0) cfg = pick_tile_cfg(dtype, m, n, k);
   return gemm_native_op(dtype, cfg, transa, transb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
                         static_cast<hipStream_t>(stream));
+}
+
+int mg_daxpy(int64_t n, double alpha, const double *x, int64_t incx, double *y, int64_t incy,
+             void *stream) {
+  clear_error();
+  if (n < 0) {
+    set_error("daxpy: negative n=%lld", (long long)n);
+    return MG_ERR_INVALID_ARG;
+  }
+  if (incx < 1 || incy < 1) {
+    set_error("daxpy: increments must be >= 1 (incx=%lld incy=%lld)", (long long)incx,
+              (long long)incy);
+    return MG_ERR_INVALID_ARG;
+  }
+  if (n == 0 || alpha == 0.0) return MG_OK;
+  if (x == nullptr || y == nullptr) {
+    set_error("daxpy: x or y is NULL");
+    return MG_ERR_INVALID_ARG;
+  }
+  if (reinterpret_cast<uintptr_t>(x) % 8 || reinterpret_cast<uintptr_t>(y) % 8) {
+    set_error("daxpy: x or y not aligned to 8 bytes");
+    return MG_ERR_INVALID_ARG;
+  }
+  const int64_t big = (int64_t)1 << 59;
+  if (n - 1 > big / incx || n - 1 > big / incy) {
+    set_error("daxpy: vector extent overflows");
+    return MG_ERR_INVALID_ARG;
+  }
+  // y may be x itself (same increment: each element reads and writes only
+  // itself); any other overlap would race.
+  if (!(x == y && incx == incy) && spans_overlap(x, 1, (n - 1) * incx + 1, 1, y, 1,
+                                                 (n - 1) * incy + 1, 1, 8)) {
+    set_error("daxpy: x and y overlap");
+    return MG_ERR_INVALID_ARG;
+  }
+  return axpy_f64(n, alpha, x, incx, y, incy, static_cast<hipStream_t>(stream));
 }
 
 int mg_gemm(int dtype, int algo, int64_t m, int64_t n, int64_t k, double alpha, const void *A,

@@ -1,0 +1,98 @@
+// DAXPY, y <- alpha*x + y (the vector kernel of the paper's conceptual
+// comparison, Section 4.1): every element is one fused multiply-add, so the
+// result is alpha*x[i] + y[i] rounded once, whatever the launch shape.
+//
+// The operation moves 24 bytes per element for 2 FLOP, far below the FP64
+// ridge point: it is bound by HBM bandwidth.  Layout on MI355X: each lane
+// moves 16-byte chunks (two doubles), a workgroup of 256 lanes covers
+// kAxpyUnroll consecutive 4 KB spans of x and y, and all loads of a lane are
+// issued before its first FMA so that 2*kAxpyUnroll 16-byte loads per lane
+// are in flight.  Operands whose addresses differ in 16-byte phase, or with
+// non-unit increments, take an element-wise kernel (8-byte accesses, still
+// coalesced for unit stride).
+#include <algorithm>
+
+#include "axpy.h"
+
+namespace mg {
+
+namespace {
+
+constexpr int kAxpyThreads = 256;
+constexpr int kAxpyUnroll = 4;
+
+// x and y 16-byte aligned after `head` (0 or 1) leading elements; pairs
+// [0, np) go through the vector path, the head and an odd last element are
+// done by lanes 0 and 1 of workgroup 0.
+__global__ __launch_bounds__(kAxpyThreads) void axpy_vec_kernel(int64_t n, int head, double alpha,
+                                                                 const double *x, double *y) {
+  const d2v *xv = reinterpret_cast<const d2v *>(x + head);
+  d2v *yv = reinterpret_cast<d2v *>(y + head);
+  const int64_t np = (n - head) >> 1;
+  const int64_t base = (int64_t)blockIdx.x * (kAxpyThreads * kAxpyUnroll) + threadIdx.x;
+  d2v a[kAxpyUnroll], b[kAxpyUnroll];
+#pragma unroll
+  for (int u = 0; u < kAxpyUnroll; ++u) {
+    const int64_t i = base + (int64_t)u * kAxpyThreads;
+    if (i < np) {
+      a[u] = __builtin_nontemporal_load(xv + i);
+      b[u] = __builtin_nontemporal_load(yv + i);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kAxpyUnroll; ++u) {
+    const int64_t i = base + (int64_t)u * kAxpyThreads;
+    if (i < np) {
+      d2v r;
+      r[0] = fma(alpha, a[u][0], b[u][0]);
+      r[1] = fma(alpha, a[u][1], b[u][1]);
+      __builtin_nontemporal_store(r, yv + i);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x < 2) {
+    int64_t j = -1;
+    if (threadIdx.x == 0 && head) j = 0;
+    if (threadIdx.x == 1 && ((n - head) & 1)) j = n - 1;
+    if (j >= 0) y[j] = fma(alpha, x[j], y[j]);
+  }
+}
+
+// Any positive increments: element i of x at x[i*incx], of y at y[i*incy].
+__global__ __launch_bounds__(kAxpyThreads) void axpy_elem_kernel(int64_t n, double alpha,
+                                                                  const double *x, int64_t incx,
+                                                                  double *y, int64_t incy) {
+  for (int64_t i = (int64_t)blockIdx.x * kAxpyThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kAxpyThreads) {
+    double *p = y + i * incy;
+    *p = fma(alpha, x[i * incx], *p);
+  }
+}
+
+}  // namespace
+
+int axpy_f64(int64_t n, double alpha, const double *x, int64_t incx, double *y, int64_t incy,
+             hipStream_t s) {
+  if (n == 0 || alpha == 0.0) return MG_OK;
+  const uintptr_t px = reinterpret_cast<uintptr_t>(x), py = reinterpret_cast<uintptr_t>(y);
+  if (incx == 1 && incy == 1 && (px & 15) == (py & 15)) {
+    const int head = (px & 15) ? 1 : 0;
+    const int64_t np = std::max<int64_t>((n - head) >> 1, 0);
+    const int64_t per_block = (int64_t)kAxpyThreads * kAxpyUnroll;
+    const int64_t blocks = std::max<int64_t>((np + per_block - 1) / per_block, 1);
+    if (blocks > INT32_MAX) {
+      set_error("axpy: n=%lld too large", (long long)n);
+      return MG_ERR_INVALID_ARG;
+    }
+    hipLaunchKernelGGL(axpy_vec_kernel, dim3((unsigned)blocks), dim3(kAxpyThreads), 0, s, n, head,
+                       alpha, x, y);
+  } else {
+    // enough workgroups to cover the chip several times, each lane striding
+    const int64_t blocks = std::min<int64_t>((n + kAxpyThreads - 1) / kAxpyThreads, 8192);
+    hipLaunchKernelGGL(axpy_elem_kernel, dim3((unsigned)blocks), dim3(kAxpyThreads), 0, s, n,
+                       alpha, x, incx, y, incy);
+  }
+  MG_HIP_TRY(hipGetLastError());
+  return MG_OK;
+}
+
+}  // namespace mg

@@ -159,3 +159,29 @@ def test_gemm_ex_empty_problem_is_ok_without_gpu():
     assert call_gemm_ex(m=0, ta=1, lda=1) == mg.OK
     assert call_gemm_ex(n=0, tb=1, C=NULL) == mg.OK
     assert mg.last_error() == ""
+
+
+def call_daxpy(n=8, alpha=1.0, x=FAKE, incx=1, y=FAKE_B, incy=1):
+    return mg.lib().mg_daxpy(n, alpha, x, incx, y, incy, NULL)
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(n=-1), "negative"),
+    (dict(incx=0), "increments"),
+    (dict(incy=-2), "increments"),
+    (dict(x=NULL), "NULL"),
+    (dict(y=NULL), "NULL"),
+    (dict(x=ctypes.c_void_p(0x10000004)), "aligned"),
+    (dict(y=ctypes.c_void_p(0x10000000 + 8 * 7)), "overlap"),        # inside x
+    (dict(y=FAKE, incy=2), "overlap"),                               # x itself, other increment
+    (dict(n=1 << 62), "overflow"),
+])
+def test_daxpy_invalid_arguments(kw, needle):
+    assert call_daxpy(**kw) == mg.ERR_INVALID_ARG
+    assert needle in mg.last_error()
+
+
+def test_daxpy_quick_returns_without_gpu():
+    assert call_daxpy(n=0, x=NULL, y=NULL) == mg.OK
+    assert call_daxpy(alpha=0.0, x=NULL, y=NULL) == mg.OK
+    assert mg.last_error() == ""

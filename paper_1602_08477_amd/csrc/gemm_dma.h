@@ -101,6 +101,9 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs<T> &g, int m0, int 
   typedef typename M::acc_t Acc;
   constexpr int ESZ = S::ESZ, VEC = S::VEC, BK = S::BK;
   constexpr int DPS = S::IA + S::IB;  // DMA instructions per k-step per wave
+  // FP64 with B in k rows: pair block columns 2p, 2p+1 on the even / odd
+  // columns of a 32-column span, so one 16-byte LDS read feeds both.
+  constexpr bool PAIR = ESZ == 8 && !TB && S::FN % 2 == 0;
   static_assert(!TA || (S::CPA >= 8 && (S::CPA & (S::CPA - 1)) == 0),
                 "transposed A rows of 2^j >= 8 chunks");
   static_assert(ESZ == 4 || (S::CPB >= 16 && (!TA || S::CPA >= 16)), "FP64 swizzle flips bit 3");
@@ -222,6 +225,26 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs<T> &g, int m0, int 
           }
         }
       }
+      if constexpr (PAIR) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          const int kr = kc * VEC + v;
+          T b[S::FN];
+#pragma unroll
+          for (int p = 0; p < S::FN / 2; ++p) {
+            const int chunk = ((wn0 + 32 * p) >> 1) + l16;  // columns wn0 + 32p + 2*l16, +1
+            const V bb = *reinterpret_cast<const V *>(Bs + kr * S::RB +
+                                                      dma_swz_b<T, S::CPB>(kr, chunk) * 16);
+            b[2 * p] = bb[0];
+            b[2 * p + 1] = bb[1];
+          }
+#pragma unroll
+          for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+            for (int j = 0; j < S::FN; ++j) acc[i][j] = M::mma(a[i][v], b[j], acc[i][j]);
+        }
+        continue;
+      }
       V bv[S::FN];  // transposed B: one chunk of VEC k values per block column
       if constexpr (TB) {
 #pragma unroll
@@ -295,7 +318,10 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs<T> &g, int m0, int 
     compute(As, Bs);
   }
 
-  Epilogue<T, true>::template store<S::FM, S::FN>(g, acc, m0 + wm0, n0 + wn0, lane);
+  if constexpr (PAIR)
+    store_paired_f64<S::FM, S::FN>(g, acc, m0 + wm0, n0 + wn0, lane);
+  else
+    Epilogue<T, true>::template store<S::FM, S::FN>(g, acc, m0 + wm0, n0 + wn0, lane);
 }
 
 }  // namespace mg

@@ -201,6 +201,52 @@ struct Epilogue<double, VEC_OK> {
   }
 };
 
+// Epilogue of the column-paired FP64 fragment layout: block columns 2p and
+// 2p+1 of a wave hold the even and odd columns of one 32-column span, so
+// lane l owns columns 32p + 2(l%16) and 32p + 2(l%16) + 1 of each of its rows:
+// one 16-byte C load and store per pair, no lane exchange.  C 16-byte aligned.
+template <int FM, int FN, int AM, int AN>
+__device__ __forceinline__ void store_paired_f64(const GemmArgs<double> &g,
+                                                 const d4v (&acc)[AM][AN], int row0, int col0,
+                                                 int lane) {
+  static_assert(FN % 2 == 0, "pairs of block columns");
+  const int gq = lane >> 4, l16 = lane & 15;
+  const bool use_c = g.beta != 0.0;
+#pragma unroll
+  for (int i = 0; i < FM; ++i) {
+    d2v c[FN / 2][4];
+#pragma unroll
+    for (int p = 0; p < FN / 2; ++p)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + 16 * i + Mfma<double>::row_of(gq, r);
+        const int col = col0 + 32 * p + 2 * l16;
+        c[p][r] = d2v{0.0, 0.0};
+        if (!use_c || row >= g.m) continue;
+        const double *q = g.C + (int64_t)row * g.ldc + col;
+        if (col + 1 < g.n) c[p][r] = *reinterpret_cast<const d2v *>(q);
+        else if (col < g.n) c[p][r][0] = q[0];
+      }
+#pragma unroll
+    for (int p = 0; p < FN / 2; ++p)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + 16 * i + Mfma<double>::row_of(gq, r);
+        const int col = col0 + 32 * p + 2 * l16;
+        if (row >= g.m) continue;
+        d2v o;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const double v = acc[i][2 * p + e][r];
+          o[e] = use_c ? fma(g.alpha, v, g.beta * c[p][r][e]) : g.alpha * v;
+        }
+        double *q = g.C + (int64_t)row * g.ldc + col;
+        if (col + 1 < g.n) *reinterpret_cast<d2v *>(q) = o;
+        else if (col < g.n) q[0] = o[0];
+      }
+  }
+}
+
 template <bool VEC_OK>
 struct Epilogue<float, VEC_OK> {
   template <int FM, int FN, int AM, int AN>

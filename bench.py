@@ -51,24 +51,28 @@ def eprint(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+DAXPY_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_daxpy_n2p27.json")
+DAXPY_SOURCES = ["paper_1602_08477_amd/csrc/axpy.hip", "paper_1602_08477_amd/csrc/common.h"]
+
+
+def kernel_source_hash(sources=None) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources or KERNEL_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_counters(launch_bytes_alg: float):
+def traffic_from_counters(launch_bytes_alg: float, path=None, sources=None):
     """HBM bytes per launch from committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     runs, scaled by the copy-kernel calibration; None if the counters were
     taken on different kernel sources."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path or TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_hash") != kernel_source_hash():
+    if t.get("kernel_source_hash") != kernel_source_hash(sources):
         return None
     return t.get("bytes_per_launch")
 
@@ -307,6 +311,9 @@ def bench_daxpy(n, steps, warmup, cpu=True, small_n=True):
            "bit_exact_vs_oracle": exact,
            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0,
                         "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
+                        "traffic": traffic_from_counters(alg_bytes, DAXPY_TRAFFIC_FILE,
+                                                         DAXPY_SOURCES)
+                        if n == 1 << 27 else None,
                         "alg_bytes_per_launch": alg_bytes, "kernel_ms": round(ms, 4)},
            "context_device_copy_gb_per_s": round(copy_gbs, 1),
            "small_n": small}
@@ -320,6 +327,23 @@ def bench_daxpy(n, steps, warmup, cpu=True, small_n=True):
     del dx, dy
     torch.cuda.empty_cache()
     return rec
+
+
+def bench_overhead():
+    """Library overhead and the naive mapping (paper Section 4.2, Figs. 5-6
+    on MI355X): runs the mg_overhead driver (C++, linked against libmg.so),
+    which times the same tiled kernel reached through mg_gemm and launched
+    directly with hipLaunchKernelGGL (device time per launch, host time per
+    enqueue), and the naive one-output-per-lane work division."""
+    import subprocess
+    from paper_1602_08477_amd import build as b
+    exe = b.driver_path(os.path.join(b.HERE, "drivers", "overhead.hip"))
+    if not os.path.exists(exe):
+        raise RuntimeError(f"{exe} is missing: build with __graft_entry__.build()")
+    r = subprocess.run([exe, "200"], capture_output=True, text=True, timeout=300)
+    if r.returncode != 0:
+        raise RuntimeError(f"mg_overhead failed ({r.returncode}): {r.stderr[-2000:]}")
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def bench_split(n, steps, warmup):
@@ -546,7 +570,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--quick", action="store_true", help="headline only (for profiling)")
-    ap.add_argument("--leg", choices=["sizes", "trans", "daxpy", "split", "batched", "serving"],
+    ap.add_argument("--leg", choices=["sizes", "trans", "daxpy", "overhead", "split", "batched",
+                                      "serving"],
                     default=None,
                     help="run only this secondary leg and print its record (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -570,6 +595,7 @@ def main():
         fn = {"split": lambda: bench_split(4096, max(3, args.steps), 1),
               "sizes": lambda: bench_sizes(args.steps, args.warmup),
               "trans": lambda: bench_trans(args.n, args.steps, args.warmup),
+              "overhead": bench_overhead,
               "daxpy": lambda: bench_daxpy(1 << 27, args.steps, args.warmup,
                                            cpu=not args.quick, small_n=not args.quick),
               "batched": lambda: bench_batched(max(3, args.steps)),
@@ -622,6 +648,8 @@ def main():
         rec["trans"] = bench_trans(n, args.steps, args.warmup)
         eprint("bench: daxpy n=2^27")
         rec["daxpy"] = bench_daxpy(1 << 27, args.steps, args.warmup)
+        eprint("bench: library overhead and naive mapping")
+        rec["overhead"] = bench_overhead()
         eprint("bench: split precision n=4096")
         rec["split"] = bench_split(4096, max(5, args.steps), 2)
         eprint("bench: batched 2000 problems")

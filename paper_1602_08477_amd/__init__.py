@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmg.so")
 
 # status codes (include/mg.h)
+NAIVE_CFG = 25  # the one-output-per-lane work division (MG_NAIVE_CFG)
 OK = 0
 PENDING = 1
 ERR_INVALID_ARG = -1

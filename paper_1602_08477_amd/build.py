@@ -1,7 +1,9 @@
 """Compiles libmg.so (HIP for gfx950) in-tree.
 
 Every source under csrc/ is compiled with hipcc to an object in _build/ (in
-parallel), then linked into paper_1602_08477_amd/libmg.so.  Always rebuilds.
+parallel), then linked into paper_1602_08477_amd/libmg.so; each program under
+drivers/ becomes paper_1602_08477_amd/mg_<name>, linked against it.  Always
+rebuilds.
 """
 
 from __future__ import annotations
@@ -43,6 +45,28 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
+def drivers() -> list[str]:
+    """Measurement programs linked against libmg.so (one executable each)."""
+    return sorted(glob.glob(os.path.join(HERE, "drivers", "*.hip")))
+
+
+def driver_path(src: str) -> str:
+    return os.path.join(HERE, "mg_" + os.path.splitext(os.path.basename(src))[0])
+
+
+def _build_driver(src: str, verbose: bool) -> str:
+    out = driver_path(src)
+    cmd = [HIPCC, "-x", "hip", *CXXFLAGS, src, "-o", out + ".tmp", "-L" + HERE, "-lmg",
+           "-Wl,-rpath,$ORIGIN"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+    os.replace(out + ".tmp", out)
+    return out
+
+
 def sources() -> list[str]:
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
@@ -61,6 +85,8 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(LIB + ".tmp", LIB)
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        list(ex.map(lambda s: _build_driver(s, verbose), drivers()))
     return LIB
 
 

@@ -4,12 +4,14 @@
 //
 // The operation moves 24 bytes per element for 2 FLOP, far below the FP64
 // ridge point: it is bound by HBM bandwidth.  Layout on MI355X: each lane
-// moves 16-byte chunks (two doubles), a workgroup of 256 lanes covers
-// kAxpyUnroll consecutive 4 KB spans of x and y, and all loads of a lane are
-// issued before its first FMA so that 2*kAxpyUnroll 16-byte loads per lane
-// are in flight.  Operands whose addresses differ in 16-byte phase, or with
-// non-unit increments, take an element-wise kernel (8-byte accesses, still
-// coalesced for unit stride).
+// moves one 16-byte chunk (two doubles) of x and of y with nontemporal
+// loads and stores (streamed data that is never reused: kept out of the
+// caches' way), one wavefront per workgroup, one workgroup per 1 KB span.
+// Measured at n = 2^27 against wider workgroups (128-1024 lanes) and more
+// chunks per lane (2-8, loads issued ahead of the FMAs): this shape keeps the
+// most requests in flight across the 256 CUs and is the fastest.  Operands
+// whose addresses differ in 16-byte phase, or with non-unit increments, take
+// an element-wise kernel (8-byte accesses, still coalesced for unit stride).
 #include <algorithm>
 
 #include "axpy.h"
@@ -18,36 +20,27 @@ namespace mg {
 
 namespace {
 
-constexpr int kAxpyThreads = 256;
-constexpr int kAxpyUnroll = 4;
+constexpr int kAxpyThreads = 256;   // element-wise kernel
+constexpr int kAxpyVecThreads = 64;  // vector kernel: one wavefront
 
 // x and y 16-byte aligned after `head` (0 or 1) leading elements; pairs
 // [0, np) go through the vector path, the head and an odd last element are
 // done by lanes 0 and 1 of workgroup 0.
-__global__ __launch_bounds__(kAxpyThreads) void axpy_vec_kernel(int64_t n, int head, double alpha,
-                                                                 const double *x, double *y) {
+__global__ __launch_bounds__(kAxpyVecThreads) void axpy_vec_kernel(int64_t n, int head,
+                                                                    double alpha, const double *x,
+                                                                    double *y) {
   const d2v *xv = reinterpret_cast<const d2v *>(x + head);
   d2v *yv = reinterpret_cast<d2v *>(y + head);
   const int64_t np = (n - head) >> 1;
-  const int64_t base = (int64_t)blockIdx.x * (kAxpyThreads * kAxpyUnroll) + threadIdx.x;
-  d2v a[kAxpyUnroll], b[kAxpyUnroll];
-#pragma unroll
-  for (int u = 0; u < kAxpyUnroll; ++u) {
-    const int64_t i = base + (int64_t)u * kAxpyThreads;
-    if (i < np) {
-      a[u] = __builtin_nontemporal_load(xv + i);
-      b[u] = __builtin_nontemporal_load(yv + i);
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < kAxpyUnroll; ++u) {
-    const int64_t i = base + (int64_t)u * kAxpyThreads;
-    if (i < np) {
-      d2v r;
-      r[0] = fma(alpha, a[u][0], b[u][0]);
-      r[1] = fma(alpha, a[u][1], b[u][1]);
-      __builtin_nontemporal_store(r, yv + i);
-    }
+  // one pass for any n below 2^31 pairs; longer vectors loop over the grid
+  for (int64_t i = (int64_t)blockIdx.x * kAxpyVecThreads + threadIdx.x; i < np;
+       i += (int64_t)gridDim.x * kAxpyVecThreads) {
+    const d2v a = __builtin_nontemporal_load(xv + i);
+    const d2v b = __builtin_nontemporal_load(yv + i);
+    d2v r;
+    r[0] = fma(alpha, a[0], b[0]);
+    r[1] = fma(alpha, a[1], b[1]);
+    __builtin_nontemporal_store(r, yv + i);
   }
   if (blockIdx.x == 0 && threadIdx.x < 2) {
     int64_t j = -1;
@@ -77,14 +70,11 @@ int axpy_f64(int64_t n, double alpha, const double *x, int64_t incx, double *y, 
   if (incx == 1 && incy == 1 && (px & 15) == (py & 15)) {
     const int head = (px & 15) ? 1 : 0;
     const int64_t np = std::max<int64_t>((n - head) >> 1, 0);
-    const int64_t per_block = (int64_t)kAxpyThreads * kAxpyUnroll;
-    const int64_t blocks = std::max<int64_t>((np + per_block - 1) / per_block, 1);
-    if (blocks > INT32_MAX) {
-      set_error("axpy: n=%lld too large", (long long)n);
-      return MG_ERR_INVALID_ARG;
-    }
-    hipLaunchKernelGGL(axpy_vec_kernel, dim3((unsigned)blocks), dim3(kAxpyThreads), 0, s, n, head,
-                       alpha, x, y);
+    // the dispatch's work-item count is 32-bit: at most 2^25 one-wave workgroups
+    const int64_t blocks = std::min<int64_t>(
+        std::max<int64_t>((np + kAxpyVecThreads - 1) / kAxpyVecThreads, 1), (int64_t)1 << 25);
+    hipLaunchKernelGGL(axpy_vec_kernel, dim3((unsigned)blocks), dim3(kAxpyVecThreads), 0, s, n,
+                       head, alpha, x, y);
   } else {
     // enough workgroups to cover the chip several times, each lane striding
     const int64_t blocks = std::min<int64_t>((n + kAxpyThreads - 1) / kAxpyThreads, 8192);

@@ -36,13 +36,49 @@ __global__ __launch_bounds__((DmaShape<T, BM, BN, WGM, WGN, NS>::THREADS),
   gemm_dma_tile<T, BM, BN, WGM, WGN, NS, TA, TB>(g, tm * BM, tn * BN, lds);
 }
 
+// The textbook mapping without the paper's hierarchy below the thread: one
+// output per lane, no shared memory, the k loop reading A and B straight
+// from global memory (the naive triple loop of Section 4.2's portability
+// experiment).  Lanes of a 16 x 16 workgroup take consecutive columns, so
+// B and C accesses coalesce and A values are shared by a row of lanes.
+// The sum runs in increasing k with one FMA per term.
+constexpr int kNaiveDim = 16;
+
+template <typename T, bool TA, bool TB>
+__global__ __launch_bounds__(kNaiveDim *kNaiveDim) void gemm_naive_kernel(GemmArgs<T> g) {
+  const int j = blockIdx.x * kNaiveDim + threadIdx.x;
+  const int i = blockIdx.y * kNaiveDim + threadIdx.y;
+  if (i >= g.m || j >= g.n) return;
+  T s = T(0);
+  for (int p = 0; p < g.k; ++p) {
+    const T a = TA ? g.A[(int64_t)p * g.lda + i] : g.A[(int64_t)i * g.lda + p];
+    const T b = TB ? g.B[(int64_t)j * g.ldb + p] : g.B[(int64_t)p * g.ldb + j];
+    s = fma(a, b, s);
+  }
+  T *c = g.C + (int64_t)i * g.ldc + j;
+  *c = g.beta != T(0) ? fma(g.alpha, s, g.beta * *c) : g.alpha * s;
+}
+
+template <typename T, bool TA, bool TB>
+int launch_naive(const GemmArgs<T> &g, hipStream_t s) {
+  const int64_t bx = (g.n + kNaiveDim - 1) / kNaiveDim, by = (g.m + kNaiveDim - 1) / kNaiveDim;
+  if (by > 65535 || bx * by * kNaiveDim * kNaiveDim > (int64_t)UINT32_MAX) {
+    set_error("naive work division: %d x %d outputs exceed one dispatch", g.m, g.n);
+    return MG_ERR_INVALID_ARG;
+  }
+  hipLaunchKernelGGL((gemm_naive_kernel<T, TA, TB>), dim3((unsigned)bx, (unsigned)by),
+                     dim3(kNaiveDim, kNaiveDim), 0, s, g);
+  MG_HIP_TRY(hipGetLastError());
+  return MG_OK;
+}
+
 template <typename T, int BM, int BN, bool VEC_OK, int WGM, int WGN, int BKM, bool TA, bool TB>
 int launch_one(const GemmArgs<T> &g, hipStream_t s) {
   typedef TileShape<T, BM, BN, WGM, WGN, BKM, TA, TB> S;
   const int tiles_m = (g.m + BM - 1) / BM, tiles_n = (g.n + BN - 1) / BN;
   const int64_t tiles = (int64_t)tiles_m * tiles_n;
-  if (tiles > INT32_MAX) {
-    set_error("too many tiles (%lld)", (long long)tiles);
+  if (tiles * S::THREADS > (int64_t)UINT32_MAX) {  // 32-bit work-item count per dispatch
+    set_error("too many tiles (%lld) for one dispatch", (long long)tiles);
     return MG_ERR_INVALID_ARG;
   }
   auto kern = gemm_native_kernel<T, BM, BN, VEC_OK, WGM, WGN, BKM, TA, TB>;
@@ -64,8 +100,8 @@ int launch_dma(const GemmArgs<T> &g, hipStream_t s) {
   typedef DmaShape<T, BM, BN, WGM, WGN, NS> S;
   const int tiles_m = (g.m + BM - 1) / BM, tiles_n = (g.n + BN - 1) / BN;
   const int64_t tiles = (int64_t)tiles_m * tiles_n;
-  if (tiles > INT32_MAX) {
-    set_error("too many tiles (%lld)", (long long)tiles);
+  if (tiles * S::THREADS > (int64_t)UINT32_MAX) {  // 32-bit work-item count per dispatch
+    set_error("too many tiles (%lld) for one dispatch", (long long)tiles);
     return MG_ERR_INVALID_ARG;
   }
   auto kern = gemm_dma_kernel<T, BM, BN, WGM, WGN, NS, TA, TB>;
@@ -84,7 +120,8 @@ int launch_dma(const GemmArgs<T> &g, hipStream_t s) {
 
 // Work divisions 0-13 stage A and B through registers; 14-24 load them
 // straight into an LDS ring (16-byte aligned operands only: otherwise a
-// register-staged division of the same macro-tile runs).  The host's table
+// register-staged division of the same macro-tile runs); 25 is the naive
+// one-output-per-lane mapping.  The host's table
 // of shapes (kCfgs in gemm_native.hip) lists the same divisions in order.
 template <typename T, bool V, bool TA, bool TB>
 int launch_cfg(int cfg, const GemmArgs<T> &g, hipStream_t s) {
@@ -136,6 +173,7 @@ int launch_cfg(int cfg, const GemmArgs<T> &g, hipStream_t s) {
     case 24:
       return V ? launch_dma<T, 64, 32, 2, 2, 3, TA, TB>(g, s)
                : launch_one<T, 64, 32, V, 2, 2, 1, TA, TB>(g, s);
+    case 25: return launch_naive<T, TA, TB>(g, s);
   }
   set_error("unknown tile cfg %d", cfg);
   return MG_ERR_INVALID_ARG;

@@ -24,7 +24,8 @@ struct CfgDesc {
   int bm, bn, wgm, wgn, bkm;
 };
 // Work divisions (the order of launch_cfg): macro-tile, wavefront grid,
-// k-step multiplier.  0-13 register-staged, 14-24 direct-load rings.
+// k-step multiplier.  0-13 register-staged, 14-24 direct-load rings, 25 the
+// naive mapping (a 16 x 16 workgroup of lanes, one output each).
 constexpr CfgDesc kCfgs[] = {{128, 128, 2, 2, 1}, {128, 64, 2, 2, 1}, {64, 64, 2, 2, 1},
                              {64, 32, 2, 2, 1},   {32, 32, 2, 2, 1},  {128, 128, 4, 2, 1},
                              {128, 128, 2, 4, 1}, {64, 64, 2, 2, 2},  {128, 64, 4, 2, 1},
@@ -33,8 +34,9 @@ constexpr CfgDesc kCfgs[] = {{128, 128, 2, 2, 1}, {128, 64, 2, 2, 1}, {64, 64, 2
                              {64, 32, 2, 2, 1},   {128, 64, 2, 2, 1},  {128, 128, 2, 4, 1},
                              {256, 128, 4, 4, 1},  {32, 32, 2, 2, 1},   {64, 64, 4, 2, 1},
                              {128, 128, 2, 4, 1},  {128, 128, 2, 2, 1}, {64, 64, 2, 2, 1},
-                             {64, 32, 2, 2, 1}};
+                             {64, 32, 2, 2, 1},   {16, 16, 0, 0, 0}};
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
+constexpr int kNaiveCfg = 25;  // one output per lane, no LDS (wgm/wgn/bkm unused)
 
 template <typename T>
 int scale_c(int64_t m, int64_t n, double beta, void *C, int64_t ldc, hipStream_t s) {
@@ -61,6 +63,11 @@ int tile_cfg_info(int dtype, int cfg, int *bm, int *bn, int *bk, int *threads) {
   }
   if (bm) *bm = kCfgs[cfg].bm;
   if (bn) *bn = kCfgs[cfg].bn;
+  if (cfg == kNaiveCfg) {
+    if (bk) *bk = 1;
+    if (threads) *threads = kCfgs[cfg].bm * kCfgs[cfg].bn;
+    return MG_OK;
+  }
   if (bk) *bk = kCfgs[cfg].bkm * (dtype == MG_F64 ? Mfma<double>::BK : Mfma<float>::BK);
   if (threads) *threads = 64 * kCfgs[cfg].wgm * kCfgs[cfg].wgn;
   return MG_OK;

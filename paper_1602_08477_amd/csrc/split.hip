@@ -750,8 +750,10 @@ int split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, const d
 
   unsigned char *As = w + L.a_off, *Bs = w + L.b_off;
   const int64_t cblocks = (L.np / 64) * (L.kp / 64);
-  if (cblocks > INT32_MAX) {
-    set_error("split operands too large");
+  // one workgroup of 256 lanes per row / per 64 x 64 block; the dispatch's
+  // work-item count is 32-bit
+  if (cblocks * 256 > (int64_t)UINT32_MAX || (int64_t)mp * 256 > (int64_t)UINT32_MAX) {
+    set_error("split operands too large for one dispatch");
     return MG_ERR_INVALID_ARG;
   }
   if (algo == MG_SPLIT_BF16) {

@@ -10,7 +10,9 @@ import synth
 
 # Native work divisions the library exports (mg_num_tile_cfgs); every one is
 # covered by the GPU parity tests.
-NATIVE_CFGS = 25
+NATIVE_CFGS = 26
+# The last one is the naive one-output-per-lane mapping (no LDS, no MFMA).
+NAIVE_CFG = 25
 # Of those, the ones that load 16-byte aligned operands straight into LDS.
 DMA_CFGS = (14, 15, 16, 17, 18, 19, 20, 21, 22, 23, 24)
 # Split product-kernel work divisions (mg_split_num_cfgs), all covered likewise.

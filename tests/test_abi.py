@@ -9,7 +9,7 @@ import re
 import pytest
 
 import paper_1602_08477_amd as mg
-from helpers import NATIVE_CFGS, SPLIT_CFGS
+from helpers import NAIVE_CFG, NATIVE_CFGS, SPLIT_CFGS
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
@@ -44,8 +44,13 @@ def test_version_and_cfgs():
     assert mg.num_tile_cfgs() == NATIVE_CFGS  # the GPU parity tests cover every one of them
     for c in range(mg.num_tile_cfgs()):
         info = mg.tile_cfg_info(c)
+        if c == NAIVE_CFG:
+            assert info == {"bm": 16, "bn": 16, "bk": 1, "threads": 256}
+            assert mg.tile_cfg_info(c, mg.F32) == info
+            continue
         assert info["bm"] % 32 == 0 and info["bn"] % 32 == 0 and info["threads"] in (256, 512, 1024)
         assert mg.tile_cfg_info(c, mg.F32)["bk"] == 2 * info["bk"]
+    assert mg.NAIVE_CFG == NAIVE_CFG == mg.num_tile_cfgs() - 1
     with pytest.raises(mg.MgError):
         mg.tile_cfg_info(99)
     assert mg.pick_tile_cfg(8192, 8192, 8192) == 21

@@ -72,6 +72,14 @@ int launch_naive(const GemmArgs<T> &g, hipStream_t s) {
   return MG_OK;
 }
 
+// Raises a kernel's dynamic LDS limit to what its ring needs; called through
+// a function-local static, so once per template instance and thread-safe.
+template <typename K>
+hipError_t set_max_lds(K kern, size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 template <typename T, int BM, int BN, bool VEC_OK, int WGM, int WGN, int BKM, bool TA, bool TB>
 int launch_one(const GemmArgs<T> &g, hipStream_t s) {
   typedef TileShape<T, BM, BN, WGM, WGN, BKM, TA, TB> S;
@@ -82,13 +90,8 @@ int launch_one(const GemmArgs<T> &g, hipStream_t s) {
     return MG_ERR_INVALID_ARG;
   }
   auto kern = gemm_native_kernel<T, BM, BN, VEC_OK, WGM, WGN, BKM, TA, TB>;
-  static bool attr_set = false;  // per template instance
-  if (!attr_set) {
-    MG_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)S::LDS_BYTES));
-    attr_set = true;
-  }
+  static const hipError_t attr = set_max_lds(kern, S::LDS_BYTES);  // once per instance
+  MG_HIP_TRY(attr);
   hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(S::THREADS), S::LDS_BYTES, s, g, tiles_m,
                      tiles_n);
   MG_HIP_TRY(hipGetLastError());
@@ -105,13 +108,8 @@ int launch_dma(const GemmArgs<T> &g, hipStream_t s) {
     return MG_ERR_INVALID_ARG;
   }
   auto kern = gemm_dma_kernel<T, BM, BN, WGM, WGN, NS, TA, TB>;
-  static bool attr_set = false;  // per template instance
-  if (!attr_set) {
-    MG_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)S::LDS_BYTES));
-    attr_set = true;
-  }
+  static const hipError_t attr = set_max_lds(kern, S::LDS_BYTES);  // once per instance
+  MG_HIP_TRY(attr);
   hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(S::THREADS), S::LDS_BYTES, s, g, tiles_m,
                      tiles_n);
   MG_HIP_TRY(hipGetLastError());

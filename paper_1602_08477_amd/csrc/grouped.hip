@@ -505,21 +505,38 @@ int build_t(int64_t count, const mg_problem *probs, const mg_tune_table *table, 
 
 template <typename T>
 int occupancy_t(int *cus, int *occ) {
-  static int s_cus = 0, s_occ = 0;  // per process: one device model
-  if (s_occ == 0) {
+  // Once per process (one device model), thread-safe through the static's
+  // initialisation: CU count, the kernel's LDS limit, workgroups per CU.
+  struct Occ {
+    hipError_t err;
+    const char *what;
+    int cus, occ;
+  };
+  static const Occ o = [] {
+    Occ r{hipSuccess, "", 0, 0};
     int dev = 0;
-    MG_HIP_TRY(hipGetDevice(&dev));
-    MG_HIP_TRY(hipDeviceGetAttribute(&s_cus, hipDeviceAttributeMultiprocessorCount, dev));
     const size_t lds = grouped_lds_bytes<T>();
-    MG_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(grouped_dma_kernel<T>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    int o = 0;
-    MG_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &o, reinterpret_cast<const void *>(grouped_dma_kernel<T>), kTileThreads, lds));
-    s_occ = std::max(1, o);
+    if ((r.err = hipGetDevice(&dev)) != hipSuccess) r.what = "hipGetDevice";
+    else if ((r.err = hipDeviceGetAttribute(&r.cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
+             hipSuccess)
+      r.what = "hipDeviceGetAttribute";
+    else if ((r.err = hipFuncSetAttribute(reinterpret_cast<const void *>(grouped_dma_kernel<T>),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
+             hipSuccess)
+      r.what = "hipFuncSetAttribute";
+    else if ((r.err = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                  &r.occ, reinterpret_cast<const void *>(grouped_dma_kernel<T>), kTileThreads,
+                  lds)) != hipSuccess)
+      r.what = "hipOccupancyMaxActiveBlocksPerMultiprocessor";
+    r.occ = std::max(1, r.occ);
+    return r;
+  }();
+  if (o.err != hipSuccess) {
+    set_error("%s failed: %s", o.what, hipGetErrorString(o.err));
+    return MG_ERR_HIP;
   }
-  *cus = s_cus;
-  *occ = s_occ;
+  *cus = o.cus;
+  *occ = o.occ;
   return MG_OK;
 }
 

@@ -41,7 +41,7 @@ template <typename T>
 struct GTileRec {
   GemmArgs<T> g;
   int tm, tn;
-  int cls;  // class | (C rows 16-byte aligned << 4)
+  int cls;  // class | (16-byte aligned rows: C << 4, A << 5, B << 6)
   int pad;
 };
 
@@ -108,6 +108,33 @@ struct GdSlots {
   int ia, ib;
 };
 
+// Logical k offset (elements) of 16-byte A slot u, and k row of 16-byte B
+// slot u (a 16-byte B slot covers 1 KB of the row-major block).
+template <typename T>
+__device__ __forceinline__ int gd_a16_kofs(int wave, int ia, int u, int lane) {
+  const int row = 8 * (wave * ia + u) + (lane >> 3);
+  return gd_swz_a(row, lane & 7) * (16 / (int)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ int gd_b16_krow(int wave, int ib, int u, int lane, int bn) {
+  return ((wave * ib + u) * 1024 + lane * 16) / (bn * (int)sizeof(T));
+}
+
+// Row-major B block of a 16-byte-B tile: [BK rows][BN*size B], chunk c of
+// row r stored at gd_swz_b(r, c), which puts the rows read together by the
+// four lane groups of a fragment read (2 apart for FP64, 4 for FP32) on
+// different halves of the banks.
+template <typename T>
+__device__ __forceinline__ int gd_swz_b(int row, int c, int cpb) {  // cpb: chunks per row, >= 8
+  if (sizeof(T) == 8) return c ^ ((((row >> 1) ^ (row >> 2)) & 1) << 3);
+  return c ^ ((((row >> 2) & 3) << 2) & (cpb - 1));
+}
+
+__device__ __forceinline__ void gd_dma16(const void *src, unsigned char *lds_dst) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)lds_dst, 16, 0,
+                                   0);
+}
+
 template <typename T>
 __device__ __forceinline__ int gd_a_kofs(int wave, int ia, int u, int lane) {
   constexpr int ESZ = sizeof(T), VEC = 16 / ESZ;
@@ -130,59 +157,121 @@ __device__ __forceinline__ int gd_b_col(int wave, int ib, int u, int lane, int b
   return (o >> 4) & (bn - 1);
 }
 
+// A16: A's rows are 16-byte aligned (pitch a multiple of 16 bytes, aligned
+// base): its slots become 16-byte loads, lane -> row 8q + lane/8, physical
+// chunk lane%8 holding logical chunk gd_swz_a(row, lane%8) -- the same LDS
+// contents as the 4-byte slots, in a quarter of the instructions.
+// 16-byte slots are built for FP64 only (kGd16 false: the FP32 kernel keeps
+// the 4-byte loads alone, which measured faster for it).
+template <typename T>
+constexpr bool kGd16 = sizeof(T) == 8;
+
 template <typename T>
 __device__ __forceinline__ void gd_setup(GdSlots<T> &sl, const GemmArgs<T> &g, int cls, int m0,
-                                         int n0, int wave, int lane) {
-  constexpr int ESZ = sizeof(T);
+                                         int n0, int wave, int lane, bool a16, bool b16) {
+  constexpr int ESZ = sizeof(T), VEC = 16 / ESZ;
+  a16 = kGd16<T> && a16;
+  b16 = kGd16<T> && b16;
   const int bm = gd_bm(cls), bn = gd_bn(cls);
-  sl.ia = bm / 8;
-  sl.ib = bn / 8;
+  sl.ib = b16 ? bn / 32 : bn / 8;
   const int boff = ((lane & 3) * 4) % ESZ;  // 4-byte half of an FP64 element
   const char *A = reinterpret_cast<const char *>(g.A);
   const char *B = reinterpret_cast<const char *>(g.B);
+  // Every slot is written on both paths (the unused 16-byte ones hold the
+  // 4-byte pointer): stores at fixed offsets keep the slot arrays in
+  // registers instead of private memory.
+  sl.ia = a16 ? bm / 32 : bm / 8;  // 16-byte: 8 rows per instruction, 4 waves
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
-    const int row = 2 * (wave * sl.ia + u) + (lane >> 5);
-    const int gr = min(m0 + row, g.m - 1);
-    sl.a[u] = A + ((int64_t)gr * g.lda + gd_a_kofs<T>(wave, sl.ia, u, lane)) * ESZ + boff;
+    const int row4 = 2 * (wave * (bm / 8) + u) + (lane >> 5);
+    const char *p = A + ((int64_t)min(m0 + row4, g.m - 1) * g.lda +
+                         gd_a_kofs<T>(wave, bm / 8, u, lane)) * ESZ + boff;
+    if (kGd16<T> && u < 2) {
+      const int row16 = 8 * (wave * (bm / 32) + u) + (lane >> 3);
+      const char *q = A + ((int64_t)min(m0 + row16, g.m - 1) * g.lda +
+                           gd_a16_kofs<T>(wave, bm / 32, u, lane)) * ESZ;
+      p = a16 ? q : p;
+    }
+    sl.a[u] = p;
   }
+  const int rb = bn * ESZ, last_col = ((g.n - 1) / VEC) * VEC;
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
-    const int col = gd_b_col<T>(wave, sl.ib, u, lane, bn);
-    const int gc = min(n0 + col, g.n - 1);
-    sl.b[u] = B + ((int64_t)gd_b_krow<T>(wave, sl.ib, u, lane, bn) * g.ldb + gc) * ESZ + boff;
+    const int ib4 = bn / 8;
+    const int col = gd_b_col<T>(wave, ib4, u, lane, bn);
+    const char *p = B + ((int64_t)gd_b_krow<T>(wave, ib4, u, lane, bn) * g.ldb +
+                         min(n0 + col, g.n - 1)) * ESZ + boff;
+    if (kGd16<T> && u < 2) {  // 16-byte: 1 KB (one or two k rows of the block) per instruction
+      const int o = (wave * (bn / 32) + u) * 1024 + lane * 16;
+      const int row = o / rb;
+      const int c = gd_swz_b<T>(row, (o % rb) >> 4, rb >> 4);
+      const char *q = B + ((int64_t)row * g.ldb + min(n0 + c * VEC, last_col)) * ESZ;
+      p = b16 ? q : p;
+    }
+    sl.b[u] = p;
   }
 }
 
 // Issues this wave's share of the k-step at `kbase` (A and B blocks) into
-// `stage`; returns the number of DMA instructions issued (a multiple of 4).
+// `stage`; returns the number of DMA instructions issued.
 // Whole steps add one uniform offset per slot; the last, partial step of a
 // tile clamps k to the problem's last column of A / row of B.
 template <typename T>
-__device__ __forceinline__ int gd_issue(const GdSlots<T> &sl, const GemmArgs<T> &g, int cls,
+__device__ __forceinline__ int gd_issue(const GdSlots<T> &sl, const GemmArgs<T> &g, int cls_bits,
                                         int kbase, unsigned char *stage, int wave, int lane) {
   constexpr int ESZ = sizeof(T), BK = 128 / ESZ;
+  const int cls = cls_bits & 15;
+  const bool a16 = kGd16<T> && ((cls_bits >> 5) & 1), b16 = kGd16<T> && ((cls_bits >> 6) & 1);
+  const bool whole = kbase + BK <= g.k;
   const int64_t bstep = (int64_t)kbase * g.ldb * ESZ;
-  if (kbase + BK <= g.k) {
+  if (a16) {
+    const int last_chunk = ((g.k - 1) / (16 / ESZ)) * (16 / ESZ);
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+      if (u < sl.ia) {
+        const char *src = sl.a[u] + (int64_t)kbase * ESZ;
+        if (!whole) {
+          const int ko = gd_a16_kofs<T>(wave, sl.ia, u, lane);
+          src = sl.a[u] + (int64_t)(min(kbase + ko, last_chunk) - ko) * ESZ;
+        }
+        gd_dma16(src, stage + (wave * sl.ia + u) * 1024);
+      }
+  }
+  if (b16) {
+    const int bn = gd_bn(cls);
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+      if (u < sl.ib) {
+        const char *src = sl.b[u] + bstep;
+        if (!whole) {
+          const int kr = gd_b16_krow<T>(wave, sl.ib, u, lane, bn);
+          src = sl.b[u] + (int64_t)(min(kbase + kr, g.k - 1) - kr) * g.ldb * ESZ;
+        }
+        gd_dma16(src, stage + kGdStageA + (wave * sl.ib + u) * 1024);
+      }
+  }
+  if (whole) {
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (u < sl.ia) gd_dma4(sl.a[u] + (int64_t)kbase * ESZ, stage + (wave * sl.ia + u) * 256);
+      if (!a16 && u < sl.ia)
+        gd_dma4(sl.a[u] + (int64_t)kbase * ESZ, stage + (wave * sl.ia + u) * 256);
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (u < sl.ib) gd_dma4(sl.b[u] + bstep, stage + kGdStageA + (wave * sl.ib + u) * 256);
+      if (!b16 && u < sl.ib)
+        gd_dma4(sl.b[u] + bstep, stage + kGdStageA + (wave * sl.ib + u) * 256);
   } else {
     const int klast = g.k - 1;
     const int bn = gd_bn(cls);
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (u < sl.ia) {
+      if (!a16 && u < sl.ia) {
         const int ko = gd_a_kofs<T>(wave, sl.ia, u, lane);
         gd_dma4(sl.a[u] + (int64_t)(min(kbase + ko, klast) - ko) * ESZ,
                 stage + (wave * sl.ia + u) * 256);
       }
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (u < sl.ib) {
+      if (!b16 && u < sl.ib) {
         const int kr = gd_b_krow<T>(wave, sl.ib, u, lane, bn);
         gd_dma4(sl.b[u] + (int64_t)(min(kbase + kr, klast) - kr) * g.ldb * ESZ,
                 stage + kGdStageA + (wave * sl.ib + u) * 256);
@@ -194,7 +283,9 @@ __device__ __forceinline__ int gd_issue(const GdSlots<T> &sl, const GemmArgs<T> 
 // One k-step of a BM x BN tile from an LDS stage.  TAIL: only the first
 // `kvalid` k of the step belong to the problem; the rest is zeroed on both
 // operands (values read from clamped addresses never reach the sums).
-template <typename T, int BM, int BN, bool TAIL>
+// BROW: the step's B block is row-major (a 16-byte-B tile): one value per
+// MFMA is read instead of one 16-byte chunk of VEC k values per column.
+template <typename T, int BM, int BN, bool TAIL, bool BROW>
 __device__ __forceinline__ void gd_compute(typename Mfma<T>::acc_t (&acc)[BM / 32][BN / 32],
                                            const unsigned char *As, const unsigned char *Bs,
                                            int wave, int lane, int kvalid) {
@@ -217,21 +308,40 @@ __device__ __forceinline__ void gd_compute(typename Mfma<T>::acc_t (&acc)[BM / 3
         for (int v = 0; v < VEC; ++v) a[i][v] = kc * VEC + v < kvalid ? a[i][v] : T(0);
       }
     }
-    V b[FN];
+    if constexpr (BROW) {
 #pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      b[j] = *reinterpret_cast<const V *>(Bs + (kc * BN + wn0 + 16 * j + l16) * 16);
-      if (TAIL) {
+      for (int v = 0; v < VEC; ++v) {
+        const int kr = kc * VEC + v;
+        T b[FN];
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) b[j][v] = kc * VEC + v < kvalid ? b[j][v] : T(0);
+        for (int j = 0; j < FN; ++j) {
+          const int byte = (wn0 + 16 * j + l16) * ESZ;
+          b[j] = *reinterpret_cast<const T *>(
+              Bs + kr * (BN * ESZ) + gd_swz_b<T>(kr, byte >> 4, BN * ESZ / 16) * 16 + (byte & 15));
+          if (TAIL) b[j] = kr < kvalid ? b[j] : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acc[i][j] = M::mma(a[i][v], b[j], acc[i][j]);
       }
+    } else {
+      V b[FN];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        b[j] = *reinterpret_cast<const V *>(Bs + (kc * BN + wn0 + 16 * j + l16) * 16);
+        if (TAIL) {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) b[j][v] = kc * VEC + v < kvalid ? b[j][v] : T(0);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < VEC; ++v)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acc[i][j] = M::mma(a[i][v], b[j][v], acc[i][j]);
     }
-#pragma unroll
-    for (int v = 0; v < VEC; ++v)
-#pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = M::mma(a[i][v], b[j][v], acc[i][j]);
   }
 }
 
@@ -286,14 +396,15 @@ struct GdLoader {
     } while (lw < ntiles && (L.cls & 15) == kScaleCls);
     if (lw < ntiles) {
       const int c = L.cls & 15;
-      gd_setup<T>(sl, L.g, c, L.tm * gd_bm(c), L.tn * gd_bn(c), wave, lane);
+      gd_setup<T>(sl, L.g, c, L.tm * gd_bm(c), L.tn * gd_bn(c), wave, lane, (L.cls >> 5) & 1,
+                  (L.cls >> 6) & 1);
     }
   }
   // Issues the next k-step of the stream; returns its DMA count (0 if none).
   __device__ __forceinline__ int issue() {
     constexpr int BK = 128 / (int)sizeof(T);
     if (lw >= ntiles) return 0;
-    const int cnt = gd_issue<T>(sl, L.g, L.cls & 15, lkt * BK, lds + (li % kGdNS) * kGdStage,
+    const int cnt = gd_issue<T>(sl, L.g, L.cls, lkt * BK, lds + (li % kGdNS) * kGdStage,
                                 wave, lane);
     ++li;
     if (++lkt * BK >= L.g.k) {
@@ -307,10 +418,21 @@ struct GdLoader {
 // Waits until at most `n` (the next step's DMA count) vector memory
 // operations of this wave are outstanding: the current step has landed.
 __device__ __forceinline__ void gd_wait_next(int n) {
-  if (n >= 16) gd_wait_vmcnt<16>();
-  else if (n >= 12) gd_wait_vmcnt<12>();
-  else if (n >= 8) gd_wait_vmcnt<8>();
-  else gd_wait_vmcnt<0>();
+  // DMA instructions per step: A 8 / 4 (4-byte, 64 / 32 rows) or 2 / 1
+  // (16-byte) plus B 8 / 4 (4-byte, 64 / 32 columns) or 2 / 1 (16-byte)
+  switch (n) {
+    case 16: gd_wait_vmcnt<16>(); break;
+    case 12: gd_wait_vmcnt<12>(); break;
+    case 10: gd_wait_vmcnt<10>(); break;
+    case 9: gd_wait_vmcnt<9>(); break;
+    case 8: gd_wait_vmcnt<8>(); break;
+    case 6: gd_wait_vmcnt<6>(); break;
+    case 5: gd_wait_vmcnt<5>(); break;
+    case 4: gd_wait_vmcnt<4>(); break;
+    case 3: gd_wait_vmcnt<3>(); break;
+    case 2: gd_wait_vmcnt<2>(); break;
+    default: gd_wait_vmcnt<0>(); break;
+  }
 }
 
 // All k-steps of one tile of class (BM, BN), then its epilogue; `t` counts
@@ -326,6 +448,7 @@ __device__ __forceinline__ void gd_run_tile(GdLoader<T> &ld, const GTileRec<T> &
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = Acc{};
   const int KT = (C.g.k + BK - 1) / BK;
+  const bool brow = kGd16<T> && ((C.cls >> 6) & 1);
   for (int kt = 0; kt < KT; ++kt) {
     gd_wait_next(ld.q1);
     __builtin_amdgcn_s_barrier();
@@ -333,8 +456,15 @@ __device__ __forceinline__ void gd_run_tile(GdLoader<T> &ld, const GTileRec<T> &
     const unsigned char *As = ld.lds + (t % kGdNS) * kGdStage;
     const unsigned char *Bs = As + kGdStageA;
     const int kvalid = C.g.k - kt * BK;
-    if (kvalid >= BK) gd_compute<T, BM, BN, false>(acc, As, Bs, ld.wave, ld.lane, kvalid);
-    else gd_compute<T, BM, BN, true>(acc, As, Bs, ld.wave, ld.lane, kvalid);
+    if (brow) {  // always false for FP32: the row-major path is not built there
+      if constexpr (kGd16<T>) {
+        if (kvalid >= BK) gd_compute<T, BM, BN, false, true>(acc, As, Bs, ld.wave, ld.lane, kvalid);
+        else gd_compute<T, BM, BN, true, true>(acc, As, Bs, ld.wave, ld.lane, kvalid);
+      }
+    } else {
+      if (kvalid >= BK) gd_compute<T, BM, BN, false, false>(acc, As, Bs, ld.wave, ld.lane, kvalid);
+      else gd_compute<T, BM, BN, true, false>(acc, As, Bs, ld.wave, ld.lane, kvalid);
+    }
     ld.q0 = ld.q1;
     ld.q1 = cnew;
     ++t;
@@ -464,11 +594,17 @@ int build_t(int64_t count, const mg_problem *probs, const mg_tune_table *table, 
     int cls = table ? table->cls[tune_bucket(q.m, q.n, q.k)] : heuristic_class(q.m, q.n);
     if (cls < 0 || cls >= kNumGroupedClasses) cls = heuristic_class(q.m, q.n);
     const bool c_vec = vec_aligned(q.C, q.ldc, sizeof(T), Mfma<T>::VEC);
+    const bool a_vec = vec_aligned(q.A, q.lda, sizeof(T), Mfma<T>::VEC);
+    // 16-byte B loads (row-major B block) for FP64 only: FP32 reads that
+    // layout one value per MFMA, four per 16-byte chunk, which measured
+    // slower than its 4-byte loads into the k-interleaved block.
+    const bool b_vec = sizeof(T) == 8 && vec_aligned(q.B, q.ldb, sizeof(T), Mfma<T>::VEC);
     const int bm = kClsBM[cls], bn = kClsBN[cls];
     const int tm = (int)ceil_div(q.m, bm), tn = (int)ceil_div(q.n, bn);
     for (int a = 0; a < tm; ++a)
       for (int b = 0; b < tn; ++b) {
-        tiles.push_back(GTileRec<T>{g, a, b, cls | (c_vec ? 16 : 0), 0});
+        tiles.push_back(
+            GTileRec<T>{g, a, b, cls | (c_vec ? 16 : 0) | (a_vec ? 32 : 0) | (b_vec ? 64 : 0), 0});
         // MFMA work of the padded tile plus its operand traffic (in FLOP-equivalents)
         cost.push_back(2.0 * bm * bn * (double)round_up(q.k, Mfma<T>::BK) +
                        16.0 * (bm + bn) * (double)q.k);

@@ -74,6 +74,56 @@ def test_tile_classes_agree_bitwise():
         assert all(torch.equal(a, b) for a, b in zip(outs[0], o))
 
 
+def padded_copy(X, aligned, dtype):
+    """X in a buffer whose row pitch is a multiple of 8 elements (16-byte rows
+    for FP64 and FP32) or odd; the padding holds NaN."""
+    r, c = X.shape
+    pitch = (c + 7) // 8 * 8 + 8 if aligned else c + 1 + (c % 2)
+    big = torch.full((r, pitch), float("nan"), dtype=dtype, device="cuda")
+    big[:, :c] = X
+    return big, big[:, :c]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_operand_alignment_paths_agree_bitwise(dt):
+    """A with 16-byte rows streams through 16-byte loads (so does FP64 B,
+    which then lands row-major in LDS), odd pitches through 4-byte loads;
+    every class gives the same bits for all four combinations (m, n, k
+    ragged against the 16-byte chunks and the tiles)."""
+    dtype = torch.float64 if dt == "f64" else torch.float32
+    code = mg.F64 if dt == "f64" else mg.F32
+    shapes = [(97, 131, 78), (200, 64, 300), (31, 257, 46), (64, 64, 16), (5, 3, 2), (70, 33, 129)]
+    for c in range(mg.NUM_GROUPED_CLASSES):
+        t = mg.TuneTable.from_list(code, [c] * mg.TUNE_BUCKETS)
+        outs = []
+        for a_al, b_al in ((True, True), (False, False), (True, False), (False, True)):
+            probs, Cs, keep = [], [], []
+            for i, (m_, n_, k_) in enumerate(shapes):
+                A = synth.matrix(85 + i, 0, m_, k_, device="cuda").to(dtype)
+                B = synth.matrix(85 + i, 1, k_, n_, device="cuda").to(dtype)
+                C = synth.matrix(85 + i, 2, m_, n_, device="cuda").to(dtype)
+                Abig, Av = padded_copy(A, a_al, dtype)
+                Bbig, Bv = padded_copy(B, b_al, dtype)
+                keep += [Abig, Bbig]
+                probs.append(mg.problem(Av, Bv, C, 1.25, 0.5))
+                Cs.append(C)
+            plan = mg.Plan(code, probs, t)
+            plan.launch()
+            torch.cuda.synchronize()
+            outs.append([C.clone() for C in Cs])
+            plan.close()
+        for o in outs[1:]:
+            assert all(torch.equal(a, b) for a, b in zip(outs[0], o)), (dt, c)
+        # and against the oracle, so that all four are not wrong alike
+        if dt == "f64":
+            for i, (m_, n_, k_) in enumerate(shapes):
+                A = synth.matrix(85 + i, 0, m_, k_)
+                B = synth.matrix(85 + i, 1, k_, n_)
+                C0 = synth.matrix(85 + i, 2, m_, n_)
+                check_problem(torch.from_numpy(A), torch.from_numpy(B), torch.from_numpy(C0),
+                              outs[0][i], 1.25, 0.5)
+
+
 def test_graph_replays_match_eager():
     shapes = [tuple(int(x) for x in s) for s in synth.batch_shapes(83, 40, 16, 256)]
     views, flats, probs = make_batch(83, shapes, beta=0.0)

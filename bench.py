@@ -172,7 +172,8 @@ def bench_native(n, steps, warmup):
 
 def bench_sizes(steps, warmup):
     """The square size sweep (n = 512 with alpha = 1.5, beta = 0.5; n = 1024 ...
-    4096 and (8192, 1024, 4096) with alpha = beta = 1), default work division:
+    4096, (8192, 1024, 4096) and the 8-GPU row-panel shard (1024, 8192, 8192)
+    with alpha = beta = 1), default work division:
     median kernel time from HIP events, warm operands; for n <= 2048 also a
     cold time with the L2 and MALL flushed by a 512 MiB write before each
     launch.  For context only, the platform BLAS (torch.addmm) is timed the
@@ -186,6 +187,8 @@ def bench_sizes(steps, warmup):
     cases = [((512, 512, 512), 1.5, 0.5, 1)] + [((n, n, n), 1.0, 1.0, 2)
                                                 for n in (1024, 2048, 4096)]
     cases.append(((8192, 1024, 4096), 1.0, 1.0, 2))
+    # one GPU's shard of the n = 8192 product split over 8 GPUs by row panels
+    cases.append(((1024, 8192, 8192), 1.0, 1.0, 2))
     for (m, n, k), alpha, beta, cfg_id in cases:
         seed = synth.config_seed(cfg_id)
         dA = synth.matrix(seed, synth.STREAM_A, m, k, device="cuda")
@@ -567,7 +570,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--quick", action="store_true", help="headline only (for profiling)")
     ap.add_argument("--leg", choices=["sizes", "trans", "daxpy", "overhead", "split", "batched",

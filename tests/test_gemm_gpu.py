@@ -182,7 +182,7 @@ def test_native_f32_parity(cfg, shape):
 
 
 @pytest.mark.parametrize("mnk", [(1024, 1024, 1024), (2048, 2048, 2048), (4096, 4096, 4096),
-                                 (8192, 8192, 8192), (8192, 1024, 4096)])
+                                 (8192, 8192, 8192), (8192, 1024, 4096), (1024, 8192, 8192)])
 def test_config2_sizes_sampled(mnk):
     """Workload 2 at full size with the default work division (the bench's):
     sampled output rows/columns against the oracle, which computes each of

@@ -204,10 +204,12 @@ int mg_gemm_split_cfg(int algo, int slices, int cfg, int64_t m, int64_t n, int64
  * heuristic), builds a device work list of macro-tiles sorted longest first
  * (each record carries its problem's arguments), and on first launch
  * captures the persistent kernel in a HIP graph that later launches replay.
- * The grid is (CUs x occupancy) workgroups; workgroup b computes tiles b,
- * b+G, b+2G, ... of the list (blocks are independent and never synchronise,
- * Section 3.2), so a problem's result is the same whatever else is in the
- * batch.
+ * The grid is (CUs x occupancy) workgroups G; the list is dealt in rounds
+ * of G tiles whose direction alternates (workgroup b takes tile b of round
+ * 0, G-1-b of round 1, ...).  Blocks are independent and never synchronise
+ * (Section 3.2), and every tile runs the single-problem kernel's k order, so
+ * a problem's result is the same whatever else is in the batch (bit for bit
+ * equal to mg_gemm on it alone).
  * Problems may share A and B; no C may overlap another problem's C, A or B
  * (checked on the byte spans [first element, last element], so interleaved
  * sub-blocks of one buffer are rejected).  dtype MG_F64 or MG_F32. */

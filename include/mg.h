@@ -82,8 +82,8 @@ int mg_gemm(int dtype, int algo, int64_t m, int64_t n, int64_t k, double alpha,
 
 /* Work divisions of the native kernel.  Configuration `cfg` in
  * [0, mg_num_tile_cfgs()) is a macro-tile of bm x bn outputs per workgroup
- * with a k-step of bk, computed by `threads` lanes.  The last one
- * (MG_NAIVE_CFG) is the naive mapping of the paper's portability experiment
+ * with a k-step of bk, computed by `threads` lanes.  MG_NAIVE_CFG (25) is
+ * the naive mapping of the paper's portability experiment
  * (Section 4.2, Fig. 6): one output per lane, a 16 x 16 workgroup, no shared
  * memory, the k loop reading global memory (bm = bn = 16, bk = 1, threads =
  * 256; at most 65535 * 16 rows).  Returns MG_OK or MG_ERR_INVALID_ARG for an

@@ -104,6 +104,9 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs<T> &g, int m0, int 
   // FP64 with B in k rows: pair block columns 2p, 2p+1 on the even / odd
   // columns of a 32-column span, so one 16-byte LDS read feeds both.
   constexpr bool PAIR = ESZ == 8 && !TB && S::FN % 2 == 0;
+  // FP64 with A in k rows (transposed A): pair block rows 2p, 2p+1 on the
+  // even / odd rows of a 32-row span the same way.
+  constexpr bool PAIRA = ESZ == 8 && TA && S::FM % 2 == 0;
   static_assert(!TA || (S::CPA >= 8 && (S::CPA & (S::CPA - 1)) == 0),
                 "transposed A rows of 2^j >= 8 chunks");
   static_assert(ESZ == 4 || (S::CPB >= 16 && (!TA || S::CPA >= 16)), "FP64 swizzle flips bit 3");
@@ -215,6 +218,18 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs<T> &g, int m0, int 
         const int row = wm0 + 16 * i + l16;
         if constexpr (!TA) {
           a[i] = *reinterpret_cast<const V *>(As + row * 128 + dma_swz_a(row, kc) * 16);
+        } else if constexpr (PAIRA) {
+          if (i % 2 == 0) {  // rows wm0 + 32p + 2*l16 (block 2p) and +1 (block 2p+1)
+            const int chunk = ((wm0 + 16 * i) >> 1) + l16;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+              const int kr = kc * VEC + v;
+              const V aa = *reinterpret_cast<const V *>(As + kr * S::RA +
+                                                        dma_swz_b<T, S::CPA>(kr, chunk) * 16);
+              a[i][v] = aa[0];
+              a[i + 1][v] = aa[1];
+            }
+          }
         } else {
           const int byte = row * ESZ;
 #pragma unroll
@@ -319,7 +334,10 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs<T> &g, int m0, int 
   }
 
   if constexpr (PAIR)
-    store_paired_f64<S::FM, S::FN>(g, acc, m0 + wm0, n0 + wn0, lane);
+    store_paired_f64<S::FM, S::FN, S::FM, S::FN, PAIRA>(g, acc, m0 + wm0, n0 + wn0, lane);
+  else if constexpr (ESZ == 8)
+    Epilogue<T, true>::template store<S::FM, S::FN, S::FM, S::FN, PAIRA>(g, acc, m0 + wm0,
+                                                                          n0 + wn0, lane);
   else
     Epilogue<T, true>::template store<S::FM, S::FN>(g, acc, m0 + wm0, n0 + wn0, lane);
 }

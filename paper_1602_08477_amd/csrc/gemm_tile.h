@@ -129,6 +129,15 @@ __device__ __forceinline__ double dpp_swap1(double x) {
   return __hiloint2double(hi2, lo2);
 }
 
+// Output row of accumulator register r of lane group gq in block row i.
+// PA (paired block rows, FP64 direct-load tiles with a transposed A): block
+// rows 2p and 2p+1 hold the even and odd rows of a 32-row span.
+template <bool PA>
+__device__ __forceinline__ int f64_out_row(int row0, int i, int gq, int r) {
+  return PA ? row0 + 32 * (i >> 1) + 2 * Mfma<double>::row_of(gq, r) + (i & 1)
+            : row0 + 16 * i + Mfma<double>::row_of(gq, r);
+}
+
 // C tile epilogue for a wave's FM x FN grid of 16x16 blocks whose top-left
 // output is (row0, col0): out = alpha*acc + beta*C (C unread when beta == 0).
 // In block (i, j), lane l holds column l%16 of rows row_of(l/16, r).  One
@@ -142,7 +151,7 @@ struct Epilogue;
 
 template <bool VEC_OK>
 struct Epilogue<double, VEC_OK> {
-  template <int FM, int FN, int AM, int AN>
+  template <int FM, int FN, int AM, int AN, bool PA = false>
   __device__ static __forceinline__ void store(const GemmArgs<double> &g,
                                                const d4v (&acc)[AM][AN], int row0, int col0,
                                                int lane) {
@@ -166,7 +175,7 @@ struct Epilogue<double, VEC_OK> {
       for (int jb = 0; jb < FN; ++jb)
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const int row = row0 + 16 * i + Mfma<double>::row_of(gq, 2 * h + (odd ? 1 : 0));
+          const int row = f64_out_row<PA>(row0, i, gq, 2 * h + (odd ? 1 : 0));
           const int col = col0 + 16 * jb + (j & ~1);
           c[jb][h] = d2v{0.0, 0.0};
           if (!use_c || row >= g.m) continue;
@@ -182,7 +191,7 @@ struct Epilogue<double, VEC_OK> {
       for (int jb = 0; jb < FN; ++jb)
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const int row = row0 + 16 * i + Mfma<double>::row_of(gq, 2 * h + (odd ? 1 : 0));
+          const int row = f64_out_row<PA>(row0, i, gq, 2 * h + (odd ? 1 : 0));
           const int col = col0 + 16 * jb + (j & ~1);
           if (row >= g.m) continue;
           d2v o;
@@ -205,7 +214,7 @@ struct Epilogue<double, VEC_OK> {
 // 2p+1 of a wave hold the even and odd columns of one 32-column span, so
 // lane l owns columns 32p + 2(l%16) and 32p + 2(l%16) + 1 of each of its rows:
 // one 16-byte C load and store per pair, no lane exchange.  C 16-byte aligned.
-template <int FM, int FN, int AM, int AN>
+template <int FM, int FN, int AM, int AN, bool PA = false>
 __device__ __forceinline__ void store_paired_f64(const GemmArgs<double> &g,
                                                  const d4v (&acc)[AM][AN], int row0, int col0,
                                                  int lane) {
@@ -219,7 +228,7 @@ __device__ __forceinline__ void store_paired_f64(const GemmArgs<double> &g,
     for (int p = 0; p < FN / 2; ++p)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = row0 + 16 * i + Mfma<double>::row_of(gq, r);
+        const int row = f64_out_row<PA>(row0, i, gq, r);
         const int col = col0 + 32 * p + 2 * l16;
         c[p][r] = d2v{0.0, 0.0};
         if (!use_c || row >= g.m) continue;
@@ -231,7 +240,7 @@ __device__ __forceinline__ void store_paired_f64(const GemmArgs<double> &g,
     for (int p = 0; p < FN / 2; ++p)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = row0 + 16 * i + Mfma<double>::row_of(gq, r);
+        const int row = f64_out_row<PA>(row0, i, gq, r);
         const int col = col0 + 32 * p + 2 * l16;
         if (row >= g.m) continue;
         d2v o;

@@ -28,10 +28,14 @@
 
 namespace mg {
 
-template <typename T, int BM, int BN, int WGM, int WGN, int NS>
+// KS = 2 runs two groups of WGM x WGN wavefronts on the same outputs, each
+// taking half of every k-step's values (16-byte k chunks 0-3 and 4-7); the
+// second group's sums are added to the first's through LDS at the end.
+template <typename T, int BM, int BN, int WGM, int WGN, int NS, int KS = 1>
 struct DmaShape {
-  static constexpr int THREADS = 64 * WGM * WGN;
-  static constexpr int WAVES = WGM * WGN;
+  static constexpr int SWAVES = WGM * WGN;     // wavefronts per k group
+  static constexpr int WAVES = SWAVES * KS;
+  static constexpr int THREADS = 64 * WAVES;
   static constexpr int ESZ = sizeof(T);
   static constexpr int VEC = 16 / ESZ;
   static constexpr int BK = 128 / ESZ;
@@ -41,7 +45,9 @@ struct DmaShape {
   static constexpr int CPA = RA / 16;
   static constexpr int A_BYTES = BM * 128;
   static constexpr int STAGE = A_BYTES + 128 * BN;  // B block: BK rows of RB bytes
-  static constexpr size_t LDS_BYTES = (size_t)NS * STAGE;
+  static constexpr size_t RING_BYTES = (size_t)NS * STAGE;
+  static constexpr size_t RED_BYTES = KS > 1 ? (size_t)BM * BN * ESZ : 0;  // k-group sums
+  static constexpr size_t LDS_BYTES = RING_BYTES > RED_BYTES ? RING_BYTES : RED_BYTES;
   static constexpr int IA = BM / 8 / WAVES;    // 1 KB DMA instructions per wave, A
   static constexpr int IB = BN / 8 / WAVES;    // and B
   static constexpr int WM = BM / WGM, WN = BN / WGN;
@@ -51,6 +57,7 @@ struct DmaShape {
   static_assert(FM >= 1 && FN >= 1 && WM % 16 == 0 && WN % 16 == 0, "16x16 blocks per wave");
   static_assert(CPB >= 8 && (CPB & (CPB - 1)) == 0, "B rows of 2^j >= 8 chunks");
   static_assert(NS >= 2 && LDS_BYTES <= 160 * 1024, "ring fits in LDS");
+  static_assert(KS == 1 || KS == 2, "one or two k groups");
   // Wavefronts per SIMD the register allocation must leave room for (the
   // second __launch_bounds__ value): as many workgroups as the LDS ring
   // allows per CU, counted up to 2 per SIMD so large register tiles (a
@@ -92,10 +99,11 @@ __device__ __forceinline__ void dma_wait_steps(int q) {
   else dma_wait_vmcnt<3 * DPS>();
 }
 
-template <typename T, int BM, int BN, int WGM, int WGN, int NS, bool TA = false, bool TB = false>
+template <typename T, int BM, int BN, int WGM, int WGN, int NS, bool TA = false, bool TB = false,
+          int KS = 1>
 __device__ __forceinline__ void gemm_dma_tile(const GemmArgs<T> &g, int m0, int n0,
                                               unsigned char *lds) {
-  typedef DmaShape<T, BM, BN, WGM, WGN, NS> S;
+  typedef DmaShape<T, BM, BN, WGM, WGN, NS, KS> S;
   typedef Mfma<T> M;
   typedef typename M::vec_t V;
   typedef typename M::acc_t Acc;
@@ -114,7 +122,8 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs<T> &g, int m0, int 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm0 = (wave / WGN) * S::WM, wn0 = (wave % WGN) * S::WN;
+  const int sw = wave % S::SWAVES, kg = wave / S::SWAVES;  // output block, k group
+  const int wm0 = (sw / WGN) * S::WM, wn0 = (sw % WGN) * S::WN;
   const int gq = lane >> 4, l16 = lane & 15;
 
   // Source of this lane's chunk in every DMA slot, without the k-step offset.
@@ -210,8 +219,9 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs<T> &g, int m0, int 
 
   auto compute = [&](const unsigned char *As, const unsigned char *Bs) {
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int kc = 4 * r + gq;  // this lane group's 16-byte k chunk
+    for (int rr = 0; rr < 2 / KS; ++rr) {
+      const int r = KS == 2 ? kg : rr;  // with two k groups, this group's half of the step
+      const int kc = 4 * r + gq;        // this lane group's 16-byte k chunk
       V a[S::FM];
 #pragma unroll
       for (int i = 0; i < S::FM; ++i) {
@@ -331,6 +341,30 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs<T> &g, int m0, int 
       __syncthreads();
     }
     compute(As, Bs);
+  }
+
+  if constexpr (KS == 2) {
+    // k group 1 hands its sums to group 0 through LDS (the ring is free once
+    // every wave is past its last step); group 0 adds them and stores.
+    constexpr int NA = sizeof(Acc) / sizeof(T);
+    T *red = reinterpret_cast<T *>(lds) + (size_t)sw * S::FM * S::FN * NA * 64 + lane;
+    __syncthreads();
+    if (kg == 1) {
+#pragma unroll
+      for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < S::FN; ++j)
+#pragma unroll
+          for (int e = 0; e < NA; ++e) red[((i * S::FN + j) * NA + e) * 64] = acc[i][j][e];
+    }
+    __syncthreads();
+    if (kg == 1) return;
+#pragma unroll
+    for (int i = 0; i < S::FM; ++i)
+#pragma unroll
+      for (int j = 0; j < S::FN; ++j)
+#pragma unroll
+        for (int e = 0; e < NA; ++e) acc[i][j][e] += red[((i * S::FN + j) * NA + e) * 64];
   }
 
   if constexpr (PAIR)

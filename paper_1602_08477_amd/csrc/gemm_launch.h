@@ -25,15 +25,15 @@ __global__ __launch_bounds__((TileShape<T, BM, BN, WGM, WGN, BKM>::THREADS)) voi
   gemm_tile<T, BM, BN, VEC_OK, WGM, WGN, BKM, TA, TB>(g, tm * BM, tn * BN, smem);
 }
 
-template <typename T, int BM, int BN, int WGM, int WGN, int NS, bool TA, bool TB>
-__global__ __launch_bounds__((DmaShape<T, BM, BN, WGM, WGN, NS>::THREADS),
-                             (DmaShape<T, BM, BN, WGM, WGN, NS>::MINW)) void gemm_dma_kernel(
+template <typename T, int BM, int BN, int WGM, int WGN, int NS, bool TA, bool TB, int KS = 1>
+__global__ __launch_bounds__((DmaShape<T, BM, BN, WGM, WGN, NS, KS>::THREADS),
+                             (DmaShape<T, BM, BN, WGM, WGN, NS, KS>::MINW)) void gemm_dma_kernel(
     GemmArgs<T> g, int tiles_m, int tiles_n) {
   extern __shared__ __align__(16) unsigned char lds[];
   int tm, tn;
   const int t = xcd_remap(blockIdx.x, tiles_m * tiles_n);
   grouped_tile(t, tiles_m, tiles_n, kGroupM, tm, tn);
-  gemm_dma_tile<T, BM, BN, WGM, WGN, NS, TA, TB>(g, tm * BM, tn * BN, lds);
+  gemm_dma_tile<T, BM, BN, WGM, WGN, NS, TA, TB, KS>(g, tm * BM, tn * BN, lds);
 }
 
 // The textbook mapping without the paper's hierarchy below the thread: one
@@ -98,16 +98,16 @@ int launch_one(const GemmArgs<T> &g, hipStream_t s) {
   return MG_OK;
 }
 
-template <typename T, int BM, int BN, int WGM, int WGN, int NS, bool TA, bool TB>
+template <typename T, int BM, int BN, int WGM, int WGN, int NS, bool TA, bool TB, int KS = 1>
 int launch_dma(const GemmArgs<T> &g, hipStream_t s) {
-  typedef DmaShape<T, BM, BN, WGM, WGN, NS> S;
+  typedef DmaShape<T, BM, BN, WGM, WGN, NS, KS> S;
   const int tiles_m = (g.m + BM - 1) / BM, tiles_n = (g.n + BN - 1) / BN;
   const int64_t tiles = (int64_t)tiles_m * tiles_n;
   if (tiles * S::THREADS > (int64_t)UINT32_MAX) {  // 32-bit work-item count per dispatch
     set_error("too many tiles (%lld) for one dispatch", (long long)tiles);
     return MG_ERR_INVALID_ARG;
   }
-  auto kern = gemm_dma_kernel<T, BM, BN, WGM, WGN, NS, TA, TB>;
+  auto kern = gemm_dma_kernel<T, BM, BN, WGM, WGN, NS, TA, TB, KS>;
   static const hipError_t attr = set_max_lds(kern, S::LDS_BYTES);  // once per instance
   MG_HIP_TRY(attr);
   hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(S::THREADS), S::LDS_BYTES, s, g, tiles_m,
@@ -119,7 +119,8 @@ int launch_dma(const GemmArgs<T> &g, hipStream_t s) {
 // Work divisions 0-13 stage A and B through registers; 14-24 load them
 // straight into an LDS ring (16-byte aligned operands only: otherwise a
 // register-staged division of the same macro-tile runs); 25 is the naive
-// one-output-per-lane mapping.  The host's table
+// one-output-per-lane mapping; 26-28 are direct-load rings whose wavefronts
+// form two k groups (twice the wavefronts per output block).  The host's table
 // of shapes (kCfgs in gemm_native.hip) lists the same divisions in order.
 template <typename T, bool V, bool TA, bool TB>
 int launch_cfg(int cfg, const GemmArgs<T> &g, hipStream_t s) {
@@ -172,6 +173,15 @@ int launch_cfg(int cfg, const GemmArgs<T> &g, hipStream_t s) {
       return V ? launch_dma<T, 64, 32, 2, 2, 3, TA, TB>(g, s)
                : launch_one<T, 64, 32, V, 2, 2, 1, TA, TB>(g, s);
     case 25: return launch_naive<T, TA, TB>(g, s);
+    case 26:
+      return V ? launch_dma<T, 64, 64, 2, 2, 2, TA, TB, 2>(g, s)
+               : launch_one<T, 64, 64, V, 2, 2, 1, TA, TB>(g, s);
+    case 27:
+      return V ? launch_dma<T, 128, 64, 2, 2, 2, TA, TB, 2>(g, s)
+               : launch_one<T, 128, 64, V, 2, 2, 1, TA, TB>(g, s);
+    case 28:
+      return V ? launch_dma<T, 64, 64, 2, 2, 4, TA, TB, 2>(g, s)
+               : launch_one<T, 64, 64, V, 2, 2, 1, TA, TB>(g, s);
   }
   set_error("unknown tile cfg %d", cfg);
   return MG_ERR_INVALID_ARG;

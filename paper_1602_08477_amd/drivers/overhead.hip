@@ -151,8 +151,14 @@ void one_shape(int n, int reps, hipStream_t s, bool first) {
       direct(mg::gemm_native_kernel<double, 32, 32, true, 2, 2, 1, false, false>,
              dim3(tm * tn), S::THREADS, S::LDS_BYTES, g, tm, tn, s);
     };
-  } else if (cfg == 19 || cfg == 23 || cfg == 21) {
-    if (cfg == 19) {
+  } else if (cfg == 19 || cfg == 23 || cfg == 21 || cfg == 26) {
+    if (cfg == 26) {
+      typedef mg::DmaShape<double, 64, 64, 2, 2, 2, 2> S;
+      auto k = mg::gemm_dma_kernel<double, 64, 64, 2, 2, 2, false, false, 2>;
+      CK(hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::LDS_BYTES));
+      raw = [&, tm, tn, k] { direct(k, dim3(tm * tn), S::THREADS, S::LDS_BYTES, g, tm, tn, s); };
+    } else if (cfg == 19) {
       typedef mg::DmaShape<double, 32, 32, 2, 2, 4> S;
       auto k = mg::gemm_dma_kernel<double, 32, 32, 2, 2, 4, false, false>;
       CK(hipFuncSetAttribute(reinterpret_cast<const void *>(k),

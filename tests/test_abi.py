@@ -55,6 +55,8 @@ def test_version_and_cfgs():
         mg.tile_cfg_info(99)
     assert mg.pick_tile_cfg(8192, 8192, 8192) == 21
     assert mg.pick_tile_cfg(2048, 2048, 2048) == 21
+    assert mg.pick_tile_cfg(1024, 8192, 8192) == 21
+    assert mg.pick_tile_cfg(1024, 1024, 1024) == 26
     assert 0 <= mg.pick_tile_cfg(16, 16, 16) < mg.num_tile_cfgs()
 
 

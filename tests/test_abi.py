@@ -57,6 +57,9 @@ def test_version_and_cfgs():
     assert mg.pick_tile_cfg(2048, 2048, 2048) == 21
     assert mg.pick_tile_cfg(1024, 8192, 8192) == 21
     assert mg.pick_tile_cfg(1024, 1024, 1024) == 26
+    assert mg.pick_tile_cfg(1024, 1024, 1024, mg.F32) == 26
+    assert mg.pick_tile_cfg(512, 512, 512) == 19
+    assert mg.pick_tile_cfg(4096, 4096, 4096, mg.F32) == 22
     assert 0 <= mg.pick_tile_cfg(16, 16, 16) < mg.num_tile_cfgs()
 
 

@@ -78,18 +78,25 @@ int tile_cfg_info(int dtype, int cfg, int *bm, int *bn, int *bk, int *threads) {
 
 int pick_tile_cfg(int dtype, int64_t m, int64_t n, int64_t k) {
   (void)k;
-  // Measured on MI355X (16-byte aligned operands): 128x128 tiles with a
-  // 2-stage direct-load ring and two workgroups per CU once every CU gets a
-  // tile (n >= 2048; FP64 on 8 wavefronts: 90 % of peak at 8192; FP32 on 4
-  // wavefronts once there are four tiles per CU), then the 64x64 ring with
-  // two k groups of wavefronts (n = 1024: FP64 44-51 TFLOP/s against 40-46
-  // for the one-group ring), then the 32x32 ring (n = 512), then the small
-  // register-staged tiles.  Unaligned operands run a register-staged
+  // Measured on MI355X (16-byte aligned operands), FP64: the 128x128 ring on
+  // 8 wavefronts once it gives every CU two tiles (90 % of peak at 8192);
+  // below that the 64x64 ring on 4 wavefronts while it still gives every CU
+  // three or more tiles (n = 2048: 64.7 TFLOP/s against 64.1 for 128x128;
+  // n = 2560: 58.7 against 54.2); then the 64x64 ring with two k groups of
+  // wavefronts (n = 1024: 47 against 41-43); then the 32x32 ring (n = 512).
+  // FP32: the 128x128 ring on 4 wavefronts from four tiles per CU, on 8
+  // from one, then the same smaller tiles.  Below those the small
+  // register-staged tiles; unaligned operands run a register-staged
   // division of the same macro-tile.
   auto tiles = [&](int c) { return ceil_div(m, kCfgs[c].bm) * ceil_div(n, kCfgs[c].bn); };
   const int64_t cus = 256;
-  if (dtype == MG_F32 && tiles(22) >= 4 * cus) return 22;
-  if (tiles(21) >= cus) return 21;
+  if (dtype == MG_F32) {
+    if (tiles(22) >= 4 * cus) return 22;
+    if (tiles(21) >= cus) return 21;
+  } else {
+    if (tiles(21) >= 2 * cus) return 21;
+    if (tiles(23) >= 3 * cus) return 23;
+  }
   if (tiles(26) >= cus) return 26;
   if (tiles(19) >= cus) return 19;
   if (tiles(2) >= 2 * cus) return 2;

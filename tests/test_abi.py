@@ -54,7 +54,10 @@ def test_version_and_cfgs():
     with pytest.raises(mg.MgError):
         mg.tile_cfg_info(99)
     assert mg.pick_tile_cfg(8192, 8192, 8192) == 21
-    assert mg.pick_tile_cfg(2048, 2048, 2048) == 21
+    assert mg.pick_tile_cfg(2048, 2048, 2048) == 23
+    assert mg.pick_tile_cfg(2048, 2048, 2048, mg.F32) == 21
+    assert mg.pick_tile_cfg(4096, 4096, 4096) == 21
+    assert mg.pick_tile_cfg(8192, 1024, 4096) == 21
     assert mg.pick_tile_cfg(1024, 8192, 8192) == 21
     assert mg.pick_tile_cfg(1024, 1024, 1024) == 26
     assert mg.pick_tile_cfg(1024, 1024, 1024, mg.F32) == 26

@@ -176,8 +176,8 @@ def bench_sizes(steps, warmup):
     with alpha = beta = 1), default work division:
     median kernel time from HIP events, warm operands; for n <= 2048 also a
     cold time with the L2 and MALL flushed by a 512 MiB write before each
-    launch.  For context only, the platform BLAS (torch.addmm) is timed the
-    same way on the same operands."""
+    launch.  For context only, the platform BLAS (torch.addmm) is timed on
+    the same operands, its launches alternating with this library's."""
     import torch
     import paper_1602_08477_amd as mg
     import synth
@@ -196,14 +196,15 @@ def bench_sizes(steps, warmup):
         dC = synth.matrix(seed, synth.STREAM_C, m, n, device="cuda")
         fn = lambda: mg.gemm(dA, dB, dC, alpha, beta)  # noqa: E731
         reps = max(steps, 20)
-        per, _ = time_launches(fn, reps, warmup, stream)
-        ms = float(np.median(per))
-        flop = 2.0 * m * n * k
-        # context: the platform BLAS (torch.addmm) on the same operands
+        # context: the platform BLAS (torch.addmm) on the same operands, timed
+        # in rotation with this library's launch so both see the same clocks
         ref = torch.empty_like(dC)
-        per_v, _ = time_launches(lambda: torch.addmm(dC, dA, dB, beta=beta, alpha=alpha, out=ref),
-                                 reps, warmup, stream)
+        per, per_v = time_interleaved(
+            [fn, lambda: torch.addmm(dC, dA, dB, beta=beta, alpha=alpha, out=ref)], reps,
+            max(warmup, 5), stream)
+        ms = float(np.median(per))
         ms_v = float(np.median(per_v))
+        flop = 2.0 * m * n * k
         rec = {"m": m, "n": n, "k": k, "alpha": alpha, "beta": beta,
                "tile_cfg": mg.pick_tile_cfg(m, n, k), "ms": round(ms, 5),
                "tflops": round(flop / ms / 1e9, 3),

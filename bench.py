@@ -176,8 +176,9 @@ def bench_sizes(steps, warmup):
     with alpha = beta = 1), default work division:
     median kernel time from HIP events, warm operands; for n <= 2048 also a
     cold time with the L2 and MALL flushed by a 512 MiB write before each
-    launch.  For context only, the platform BLAS (torch.addmm) is timed on
-    the same operands, its launches alternating with this library's."""
+    launch.  For context only, the platform BLAS (in-place torch addmm_, one
+    GEMM launch per call) is timed on the same operands, its launches
+    alternating with this library's."""
     import torch
     import paper_1602_08477_amd as mg
     import synth
@@ -196,11 +197,13 @@ def bench_sizes(steps, warmup):
         dC = synth.matrix(seed, synth.STREAM_C, m, n, device="cuda")
         fn = lambda: mg.gemm(dA, dB, dC, alpha, beta)  # noqa: E731
         reps = max(steps, 20)
-        # context: the platform BLAS (torch.addmm) on the same operands, timed
-        # in rotation with this library's launch so both see the same clocks
-        ref = torch.empty_like(dC)
+        # context: the platform BLAS on the same operands, timed in rotation
+        # with this library's launch so both see the same clocks; in place on
+        # its own copy of C (C <- beta*C + alpha*A@B, one GEMM launch, no
+        # copy of C inside the timed launch)
+        ref = dC.clone()
         per, per_v = time_interleaved(
-            [fn, lambda: torch.addmm(dC, dA, dB, beta=beta, alpha=alpha, out=ref)], reps,
+            [fn, lambda: ref.addmm_(dA, dB, beta=beta, alpha=alpha)], reps,
             max(warmup, 5), stream)
         ms = float(np.median(per))
         ms_v = float(np.median(per_v))

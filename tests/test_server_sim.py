@@ -112,7 +112,9 @@ def test_continuous_batching_groups_late_arrivals():
 
 def test_batches_overlap_across_streams():
     ops = FakeOperands()
-    with mg.Server(n_streams=3, max_batch=1, simulate=True, sim_tflops=1.0,
+    # each simulated batch lasts ~3 ms, far longer than the scheduler needs
+    # to hand the next request to a free lane even on a loaded host
+    with mg.Server(n_streams=3, max_batch=1, simulate=True, sim_tflops=0.01,
                    sim_launch_ns=0) as srv:
         ts = [srv.submit_request(ops.request(256)) for _ in range(6)]
         res = [srv.wait(t) for t in ts]

@@ -119,7 +119,7 @@ int launch_dma(const GemmArgs<T> &g, hipStream_t s) {
 // Work divisions 0-13 stage A and B through registers; 14-24 load them
 // straight into an LDS ring (16-byte aligned operands only: otherwise a
 // register-staged division of the same macro-tile runs); 25 is the naive
-// one-output-per-lane mapping; 26-28 are direct-load rings whose wavefronts
+// one-output-per-lane mapping; 26-29 are direct-load rings whose wavefronts
 // form two k groups (twice the wavefronts per output block).  The host's table
 // of shapes (kCfgs in gemm_native.hip) lists the same divisions in order.
 template <typename T, bool V, bool TA, bool TB>
@@ -182,6 +182,9 @@ int launch_cfg(int cfg, const GemmArgs<T> &g, hipStream_t s) {
     case 28:
       return V ? launch_dma<T, 64, 64, 2, 2, 4, TA, TB, 2>(g, s)
                : launch_one<T, 64, 64, V, 2, 2, 1, TA, TB>(g, s);
+    case 29:
+      return V ? launch_dma<T, 64, 32, 2, 1, 2, TA, TB, 2>(g, s)
+               : launch_one<T, 64, 32, V, 2, 2, 1, TA, TB>(g, s);
   }
   set_error("unknown tile cfg %d", cfg);
   return MG_ERR_INVALID_ARG;

@@ -26,7 +26,7 @@ struct CfgDesc {
 };
 // Work divisions (the order of launch_cfg): macro-tile, wavefront grid,
 // k-step multiplier.  0-13 register-staged, 14-24 direct-load rings, 25 the
-// naive mapping (a 16 x 16 workgroup of lanes, one output each), 26-28
+// naive mapping (a 16 x 16 workgroup of lanes, one output each), 26-29
 // direct-load rings with two k groups of wavefronts.
 constexpr CfgDesc kCfgs[] = {{128, 128, 2, 2, 1}, {128, 64, 2, 2, 1}, {64, 64, 2, 2, 1},
                              {64, 32, 2, 2, 1},   {32, 32, 2, 2, 1},  {128, 128, 4, 2, 1},
@@ -37,7 +37,7 @@ constexpr CfgDesc kCfgs[] = {{128, 128, 2, 2, 1}, {128, 64, 2, 2, 1}, {64, 64, 2
                              {256, 128, 4, 4, 1},  {32, 32, 2, 2, 1},   {64, 64, 4, 2, 1},
                              {128, 128, 2, 4, 1},  {128, 128, 2, 2, 1}, {64, 64, 2, 2, 1},
                              {64, 32, 2, 2, 1},   {16, 16, 0, 0, 0},  {64, 64, 2, 2, 1, 2},
-                             {128, 64, 2, 2, 1, 2}, {64, 64, 2, 2, 1, 2}};
+                             {128, 64, 2, 2, 1, 2}, {64, 64, 2, 2, 1, 2},  {64, 32, 2, 1, 1, 2}};
 constexpr int kNumCfgs = sizeof(kCfgs) / sizeof(kCfgs[0]);
 constexpr int kNaiveCfg = 25;  // one output per lane, no LDS (wgm/wgn/bkm unused)
 
@@ -82,8 +82,10 @@ int pick_tile_cfg(int dtype, int64_t m, int64_t n, int64_t k) {
   // 8 wavefronts once it gives every CU two tiles (90 % of peak at 8192);
   // below that the 64x64 ring on 4 wavefronts while it still gives every CU
   // three or more tiles (n = 2048: 64.7 TFLOP/s against 64.1 for 128x128;
-  // n = 2560: 58.7 against 54.2); then the 64x64 ring with two k groups of
-  // wavefronts (n = 1024: 47 against 41-43); then the 32x32 ring (n = 512).
+  // n = 2560: 58.7 against 54.2); then the 64x32 ring with two k groups of
+  // wavefronts while it gives every CU four tiles (n = 1536: 49.9 against
+  // 44.6), the 64x64 one with two k groups (n = 1024: 44-47 against 41-43);
+  // then the 32x32 ring (n = 512).
   // FP32: the 128x128 ring on 4 wavefronts from four tiles per CU, on 8
   // from one, then the same smaller tiles.  Below those the small
   // register-staged tiles; unaligned operands run a register-staged
@@ -96,6 +98,7 @@ int pick_tile_cfg(int dtype, int64_t m, int64_t n, int64_t k) {
   } else {
     if (tiles(21) >= 2 * cus) return 21;
     if (tiles(23) >= 3 * cus) return 23;
+    if (tiles(29) >= 4 * cus) return 29;
   }
   if (tiles(26) >= cus) return 26;
   if (tiles(19) >= cus) return 19;

@@ -10,15 +10,15 @@ import synth
 
 # Native work divisions the library exports (mg_num_tile_cfgs); every one is
 # covered by the GPU parity tests.
-NATIVE_CFGS = 29
+NATIVE_CFGS = 30
 # The last one is the naive one-output-per-lane mapping (no LDS, no MFMA).
 NAIVE_CFG = 25
 # Of those, the ones that load 16-byte aligned operands straight into LDS.
-DMA_CFGS = (14, 15, 16, 17, 18, 19, 20, 21, 22, 23, 24, 26, 27, 28)
+DMA_CFGS = (14, 15, 16, 17, 18, 19, 20, 21, 22, 23, 24, 26, 27, 28, 29)
 # Of those, the ones with two k groups of wavefronts: each group sums half of
 # every k-step and the halves are added at the end, a fixed order of its own
 # (not the register-staged tiles' order, so not bit-identical to them).
-KGROUP_CFGS = (26, 27, 28)
+KGROUP_CFGS = (26, 27, 28, 29)
 # Split product-kernel work divisions (mg_split_num_cfgs), all covered likewise.
 SPLIT_CFGS = 15
 

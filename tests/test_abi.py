@@ -60,6 +60,7 @@ def test_version_and_cfgs():
     assert mg.pick_tile_cfg(8192, 1024, 4096) == 21
     assert mg.pick_tile_cfg(1024, 8192, 8192) == 21
     assert mg.pick_tile_cfg(1024, 1024, 1024) == 26
+    assert mg.pick_tile_cfg(1536, 1536, 1536) == 29
     assert mg.pick_tile_cfg(1024, 1024, 1024, mg.F32) == 26
     assert mg.pick_tile_cfg(512, 512, 512) == 19
     assert mg.pick_tile_cfg(4096, 4096, 4096, mg.F32) == 22

@@ -444,6 +444,28 @@ def bench_batched(steps):
                      "tiles": st["tiles"], "workgroups": st["workgroups"],
                      "tiles_per_class": st["tiles_per_class"], "autotune_s": round(tune_s, 2),
                      "gflop": round(flop / 1e9, 3), "gbytes": round(byts / 1e9, 3)}
+        if dt == torch.float64:
+            # context: the same problems with every row pitch rounded up to an
+            # even count (16-byte rows, so all tiles take the 16-byte loads)
+            ev = lambda x: -(-int(x) // 2) * 2  # noqa: E731
+            offp = {"A": [0], "B": [0], "C": [0]}
+            for m_, n_, k_ in shapes:
+                for key, sz in (("A", m_ * ev(k_)), ("B", k_ * ev(n_)), ("C", m_ * ev(n_))):
+                    offp[key].append(offp[key][-1] + -(-int(sz) // 32) * 32)
+            flp = {key: synth.flat_uniform(seed, i, offp[key][-1], device="cuda").to(dt)
+                   for i, key in enumerate(("A", "B", "C"))}
+            pp = []
+            for i, (m_, n_, k_) in enumerate(shapes):
+                m_, n_, k_ = int(m_), int(n_), int(k_)
+                A = flp["A"][offp["A"][i]: offp["A"][i] + m_ * ev(k_)].view(m_, ev(k_))[:, :k_]
+                B = flp["B"][offp["B"][i]: offp["B"][i] + k_ * ev(n_)].view(k_, ev(n_))[:, :n_]
+                C = flp["C"][offp["C"][i]: offp["C"][i] + m_ * ev(n_)].view(m_, ev(n_))[:, :n_]
+                pp.append(mg.problem(A, B, C, 1.0, 1.0))
+            plan_p = mg.Plan(code, pp, table)
+            (per_p,) = time_interleaved([lambda: plan_p.launch(graph=True)], steps, 5, stream)
+            out[name]["ms_even_row_pitch"] = round(float(np.median(per_p)), 4)
+            plan_p.close()
+            del flp, pp
         plan.close()
         plan_h.close()
         del flats, probs

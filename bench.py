@@ -159,6 +159,8 @@ def bench_native(n, steps, warmup):
     # kernel duration from events on the launch stream
     per_launch, _ = time_launches(lambda: mg.gemm(dA, dB, dC, 1.0, 1.0), steps, 1, stream)
     kern_ms = float(np.mean(per_launch))
+    spread = {f"kernel_ms_p{q}": round(float(np.percentile(per_launch, q)), 4)
+              for q in (10, 50, 90)}
 
     # parity of one fresh step
     dC.copy_(C0)
@@ -167,7 +169,7 @@ def bench_native(n, steps, warmup):
     err = sampled_error(dA, dB, C0, dC, 1.0, 1.0, seed)
     del dA, dB, dC, C0
     torch.cuda.empty_cache()
-    return ms_per_step, kern_ms, err
+    return ms_per_step, kern_ms, err, spread
 
 
 def bench_sizes(steps, warmup):
@@ -400,6 +402,23 @@ def batched_roofline_ms(shapes, esz, peak_tflops):
         float(flop.sum()), float(byts.sum())
 
 
+def batched_oracle_error(shapes, offs, flats, C_init):
+    """Largest relative Frobenius error over all problems of a batch against
+    the oracle (run on the operands as stored, FP32 widened exactly)."""
+    import oracle
+    h = {key: t.double().cpu().numpy() for key, t in flats.items()}
+    c0 = C_init.double().cpu().numpy()
+    worst = 0.0
+    for i, (m_, n_, k_) in enumerate(shapes):
+        m_, n_, k_ = int(m_), int(n_), int(k_)
+        A = h["A"][offs["A"][i]: offs["A"][i] + m_ * k_].reshape(m_, k_)
+        B = h["B"][offs["B"][i]: offs["B"][i] + k_ * n_].reshape(k_, n_)
+        C = c0[offs["C"][i]: offs["C"][i] + m_ * n_].reshape(m_, n_)
+        got = h["C"][offs["C"][i]: offs["C"][i] + m_ * n_].reshape(m_, n_)
+        worst = max(worst, oracle.rel_fro_err(got, oracle.dgemm(1.0, A, B, 1.0, C)))
+    return worst
+
+
 def bench_batched(steps):
     """2000 problems, m, n, k log-uniform in [16, 512], FP64 and FP32: one
     persistent launch per batch, graph-replayed, tile classes autotuned."""
@@ -425,6 +444,7 @@ def bench_batched(steps):
             B = flats["B"][offs["B"][i]: offs["B"][i] + k_ * n_].view(k_, n_)
             C = flats["C"][offs["C"][i]: offs["C"][i] + m_ * n_].view(m_, n_)
             probs.append(mg.problem(A, B, C, 1.0, 1.0))
+        C_init = flats["C"].clone()
         t0 = time.perf_counter()
         table = mg.autotune(code, reps=2)
         tune_s = time.perf_counter() - t0
@@ -444,6 +464,13 @@ def bench_batched(steps):
                      "tiles": st["tiles"], "workgroups": st["workgroups"],
                      "tiles_per_class": st["tiles_per_class"], "autotune_s": round(tune_s, 2),
                      "gflop": round(flop / 1e9, 3), "gbytes": round(byts / 1e9, 3)}
+        # every problem of one fresh launch against the oracle
+        flats["C"].copy_(C_init)
+        plan.launch(graph=True)
+        torch.cuda.synchronize()
+        out[name]["rel_fro_err_max_all_problems"] = float(
+            f"{batched_oracle_error(shapes, offs, flats, C_init):.3e}")
+        del C_init
         if dt == torch.float64:
             # context: the same problems with every row pitch rounded up to an
             # even count (16-byte rows, so all tiles take the 16-byte loads)
@@ -473,10 +500,52 @@ def bench_batched(steps):
     return out
 
 
-def serve_trace(mg, synth, seed, rate, seconds, pools, ring_ptr, ring, nmax, budget, table):
+def serve_offsets(ns, arena_elems):
+    """C of request i at a 256-byte aligned offset of the arena, handed out in
+    arrival order and wrapping to 0 when the rest of the arena is too small.
+    Returns (offsets, wrap number per request)."""
+    offs = np.empty(len(ns), dtype=np.int64)
+    wraps = np.empty(len(ns), dtype=np.int64)
+    cur, w = 0, 0
+    for i, n in enumerate(ns):
+        sz = -(-int(n) * int(n) // 32) * 32
+        if cur + sz > arena_elems:
+            cur, w = 0, w + 1
+        offs[i], wraps[i] = cur, w
+        cur += sz
+    return offs, wraps
+
+
+def output_conflicts(ns, offs, wraps, res):
+    """Requests whose C region was reused by a later request that the server
+    launched before this one had finished (host timestamps: t_launch is taken
+    before the batch is enqueued, t_done after its completion event fired).
+    Launches follow arrival order, so only the first later request that
+    reuses the region needs checking."""
+    ends = offs + ns.astype(np.int64) ** 2
+    launch = np.array([r.t_launch_ns for r in res])
+    done = np.array([r.t_done_ns for r in res])
+    bad = 0
+    for w in range(int(wraps.max())):
+        cur = np.nonzero(wraps == w)[0]
+        nxt = np.nonzero(wraps == w + 1)[0]
+        if len(nxt) == 0:
+            continue
+        # first request of the next wrap whose region ends past this one's start
+        pos = np.searchsorted(ends[nxt], offs[cur], side="right")
+        j = nxt[pos.clip(max=len(nxt) - 1)]
+        reuse = (pos < len(nxt)) & (offs[j] < ends[cur])
+        bad += int(np.sum(reuse & (launch[j] < done[cur])))
+    return bad
+
+
+def serve_trace(mg, synth, seed, rate, seconds, pools, arena, nmax, budget, table):
     """One open-loop replay: Poisson arrivals at ``rate``, square n
-    log-uniform in [32, 2048], 70 % native / 30 % split-INT8, operands are
-    views of resident pools; returns latency percentiles and throughput."""
+    log-uniform in [32, 2048], 70 % native / 30 % split-INT8; A and B are
+    views of resident pools, each request writes its own region of the C
+    arena.  Returns latency percentiles, throughput and the number of
+    requests whose output region a later, concurrently running request
+    reused (expected 0)."""
     count = max(1, int(rate * seconds))
     gaps = synth.poisson_gaps(seed, synth.STREAM_ARRIVALS, count, rate)
     t_arr = np.cumsum(gaps) - gaps[0]
@@ -485,16 +554,17 @@ def serve_trace(mg, synth, seed, rate, seconds, pools, ring_ptr, ring, nmax, bud
     algos = np.where(mix < 0.3, mg.SPLIT_I8, mg.NATIVE)
     pool_a, pool_b, pool_elems = pools
     offs = synth.log_uniform_int(seed, 12, count, 1, pool_elems - nmax * nmax - 1) // 32 * 32
+    c_offs, wraps = serve_offsets(ns, arena.numel())
     reqs = (mg.Request * count)()
-    base_a, base_b = pool_a.data_ptr(), pool_b.data_ptr()
+    base_a, base_b, base_c = pool_a.data_ptr(), pool_b.data_ptr(), arena.data_ptr()
     for i in range(count):
         n = int(ns[i])
         o = int(offs[i]) * 8
         reqs[i] = mg.Request(mg.F64, int(algos[i]),
                              mg.Problem(n, n, n, 1.0, 1.0, base_a + o, n, base_b + o, n,
-                                        ring_ptr + (i % ring) * nmax * nmax * 8, n),
+                                        base_c + int(c_offs[i]) * 8, n),
                              int(t_arr[i] * 1e9))
-    with mg.Server(n_streams=4, max_slots=ring, max_batch=64, hbm_budget_bytes=budget,
+    with mg.Server(n_streams=4, max_slots=256, max_batch=64, hbm_budget_bytes=budget,
                    table=table) as srv:
         res = srv.replay(reqs)
         st = srv.stats()
@@ -515,13 +585,78 @@ def serve_trace(mg, synth, seed, rate, seconds, pools, ring_ptr, ring, nmax, bud
             "mean_batch_size": round(float(bsz.mean()), 2), "batches": st["batches"],
             "max_batch": st["max_batch_seen"],
             "max_inflight_gib": round(st["max_inflight_bytes"] / 2 ** 30, 3),
-            "max_slots_used": st["max_slots_used"]}
+            "max_slots_used": st["max_slots_used"],
+            "arena_wraps": int(wraps.max()),
+            "output_conflicts": output_conflicts(ns, c_offs, wraps, res)}
+
+
+def serve_verify(mg, synth, pools, nmax, table, seconds=1.0, rate=2000.0):
+    """The workload-5 mix for ``seconds`` with every request's C in its own
+    region (no reuse), then 1 % of the requests (at least 200) against the
+    oracle: full outputs below n = 512, 16 x 16 sampled outputs above."""
+    import torch
+    import oracle
+    seed = synth.config_seed(5, 9)
+    count = int(rate * seconds)
+    gaps = synth.poisson_gaps(seed, synth.STREAM_ARRIVALS, count, rate)
+    t_arr = np.cumsum(gaps) - gaps[0]
+    ns = synth.log_uniform_int(seed, synth.STREAM_SIZES, count, 32, nmax).astype(np.int64)
+    algos = np.where(synth.uniform_unit(seed, synth.STREAM_MIX, count) < 0.3, mg.SPLIT_I8,
+                     mg.NATIVE)
+    pool_a, pool_b, pool_elems = pools
+    offs = synth.log_uniform_int(seed, 12, count, 1, pool_elems - nmax * nmax - 1) // 32 * 32
+    c_off = np.concatenate([[0], np.cumsum((ns * ns + 31) // 32 * 32)])
+    C0 = synth.flat_uniform(seed, 2, int(c_off[-1]), device="cuda")
+    C = C0.clone()
+    reqs = (mg.Request * count)()
+    for i in range(count):
+        n, o = int(ns[i]), int(offs[i]) * 8
+        reqs[i] = mg.Request(mg.F64, int(algos[i]),
+                             mg.Problem(n, n, n, 1.0, 1.0, pool_a.data_ptr() + o, n,
+                                        pool_b.data_ptr() + o, n,
+                                        C.data_ptr() + int(c_off[i]) * 8, n),
+                             int(t_arr[i] * 1e9))
+    with mg.Server(n_streams=4, max_slots=256, max_batch=64, hbm_budget_bytes=64 << 30,
+                   table=table) as srv:
+        res = srv.replay(reqs)
+    pick = np.unique((synth.uniform_unit(seed, 13, max(200, count // 100)) * count)
+                     .astype(np.int64))
+    worst = {"native": 0.0, "split_i8": 0.0}
+    checked = {"native": 0, "split_i8": 0}
+    for i in pick:
+        n = int(ns[i])
+        o = int(offs[i])
+        a = pool_a[o: o + n * n].view(n, n)
+        b = pool_b[o: o + n * n].view(n, n)
+        lo = int(c_off[i])
+        c0 = C0[lo: lo + n * n].view(n, n)
+        got = C[lo: lo + n * n].view(n, n)
+        if n < 512:
+            r = c = None
+            ref = oracle.dgemm(1.0, a.cpu().numpy(), b.cpu().numpy(), 1.0, c0.cpu().numpy())
+            g = got.cpu().numpy()
+        else:
+            r = np.unique((synth.uniform_unit(seed + int(i), 14, 16) * n).astype(np.int64))
+            c = np.unique((synth.uniform_unit(seed + int(i), 15, 16) * n).astype(np.int64))
+            rt, ct = torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda()
+            ref = oracle.dgemm(1.0, a[rt].cpu().numpy(), b[:, ct].cpu().numpy(), 1.0,
+                               c0[rt][:, ct].cpu().numpy())
+            g = got[rt][:, ct].cpu().numpy()
+        key = "native" if algos[i] == mg.NATIVE else "split_i8"
+        worst[key] = max(worst[key], oracle.rel_fro_err(g, ref))
+        checked[key] += 1
+    del C0, C
+    torch.cuda.empty_cache()
+    return {"requests": count, "completed_ok": int(sum(r.status == 0 for r in res)),
+            "checked_vs_oracle": checked,
+            "rel_fro_err_max": {k: float(f"{v:.3e}") for k, v in worst.items()}}
 
 
 def bench_serving(seconds, rate=2000.0):
     """Open-loop Poisson serving at 2000 requests/s for ``seconds`` under a
     64 GiB HBM budget; then the same mix under a 1 GiB budget (admission
-    binds), and a saturation sweep of higher arrival rates."""
+    binds), a saturation sweep of higher arrival rates, and a short trace
+    whose results are checked against the oracle."""
     import torch
     import paper_1602_08477_amd as mg
     import synth
@@ -530,10 +665,11 @@ def bench_serving(seconds, rate=2000.0):
     seed = synth.config_seed(5)
     pools = (synth.flat_uniform(seed, 0, pool_elems, device="cuda"),
              synth.flat_uniform(seed, 1, pool_elems, device="cuda"), pool_elems)
-    ring = 256
-    cbuf = torch.zeros(ring, nmax * nmax, dtype=torch.float64, device="cuda")
+    # 32 GiB of outputs: each request writes its own region until the arena
+    # wraps; output_conflicts counts any reuse while the earlier one ran
+    arena = torch.zeros(1 << 32, dtype=torch.float64, device="cuda")
     table = mg.autotune(mg.F64, reps=2)
-    args = (pools, cbuf.data_ptr(), ring, nmax)
+    args = (pools, arena, nmax)
     out = serve_trace(mg, synth, seed, rate, seconds, *args, 64 << 30, table)
     short = min(seconds, 10.0)
     out["stress_1gib"] = serve_trace(mg, synth, synth.config_seed(5, 1), rate, short, *args,
@@ -541,9 +677,24 @@ def bench_serving(seconds, rate=2000.0):
     out["saturation"] = [serve_trace(mg, synth, synth.config_seed(5, 2 + i), r,
                                      min(seconds, 3.0), *args, 64 << 30, table)
                          for i, r in enumerate((8000.0, 16000.0, 32000.0))]
-    del cbuf, pools
+    del arena
+    torch.cuda.empty_cache()
+    out["verify"] = serve_verify(mg, synth, pools, nmax, table)
+    del pools
     torch.cuda.empty_cache()
     return out
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (as lscpu reports it, from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(n, target_s=12.0):
@@ -587,7 +738,7 @@ def cpu_baseline(n, target_s=12.0):
             small[f"n{sn}_{tag}_gflops"] = round(2.0 * sn ** 3 / (time.perf_counter() - t0) / 1e9, 3)
     oracle.set_threads(cores)
     return {"value": float(f"{tflops:.6g}"), "unit": "TFLOP/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{rows} of {n} output rows of the n={n} FP64 GEMM ({dt:.1f} s)",
             "small_workloads": small}
 
@@ -633,7 +784,7 @@ def main():
         return
     n = args.n
     eprint(f"bench: native FP64 n={n} steps={args.steps} warmup={args.warmup}")
-    ms_step, kern_ms, err = bench_native(n, args.steps, args.warmup)
+    ms_step, kern_ms, err, spread = bench_native(n, args.steps, args.warmup)
     if args.copy_gib > 0:
         nb = int(args.copy_gib * 2 ** 30) // 8
         src = torch.ones(nb, dtype=torch.float64, device="cuda")
@@ -668,7 +819,7 @@ def main():
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK, 4),
                      "traffic": traffic_from_counters(alg_bytes),
                      "alg_flop_per_launch": flop, "alg_bytes_per_launch": alg_bytes,
-                     "kernel_ms": round(kern_ms, 4)},
+                     "kernel_ms": round(kern_ms, 4), **spread},
     }
     if not args.quick:
         eprint("bench: size sweep")

@@ -207,9 +207,15 @@ int mg_gemm_split_cfg(int algo, int slices, int cfg, int64_t m, int64_t n, int64
  * The grid is (CUs x occupancy) workgroups G; the list is dealt in rounds
  * of G tiles whose direction alternates (workgroup b takes tile b of round
  * 0, G-1-b of round 1, ...).  Blocks are independent and never synchronise
- * (Section 3.2), and every tile runs the single-problem kernel's k order, so
- * a problem's result is the same whatever else is in the batch (bit for bit
- * equal to mg_gemm on it alone).
+ * (Section 3.2), and every tile sums its k-steps in the order of the
+ * single-problem kernels with one k group of wavefronts, so a problem's
+ * result is the same whatever else is in the batch, and bit for bit equal to
+ * mg_gemm_cfg on it alone with any one-k-group work division (0-24).  That
+ * is also mg_gemm's own result unless mg_pick_tile_cfg picks a two-k-group
+ * division (26-29; FP64 and FP32 problems with roughly 2^20 <= m*n < 2^22,
+ * e.g. n = 1024 and 1536): those add two half-sums per output at the end, so
+ * there the batched and single results agree to the rounding bound
+ * (k+2)u(|alpha||A||B| + |beta||C|) per element, not bit for bit.
  * Problems may share A and B; no C may overlap another problem's C, A or B
  * (checked on the byte spans [first element, last element], so interleaved
  * sub-blocks of one buffer are rejected).  dtype MG_F64 or MG_F32. */
@@ -322,6 +328,15 @@ typedef struct mg_request {
   int32_t algo;           /* MG_NATIVE, or MG_SPLIT_I8 / MG_SPLIT_BF16 (F64)  */
   mg_problem p;
   int64_t t_arrival_ns;   /* scheduled arrival: latencies are measured from it */
+  /* Producer event (hipEvent_t as void*) or NULL.  The server's streams do
+   * not synchronise with the caller's, so the request's kernels are ordered
+   * after the caller's writes to A, B and C only through this event: the lane
+   * waits on it (hipStreamWaitEvent) before it launches the batch holding the
+   * request.  The caller records it after those writes and keeps it alive and
+   * un-recorded until the request is reported done.  With NULL the caller must
+   * have finished every write to A, B and C (e.g. synchronised the producing
+   * stream) before the call to mg_gemm_submit. */
+  void *ready_event;
 } mg_request;
 
 typedef struct mg_result {

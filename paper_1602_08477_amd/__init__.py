@@ -382,7 +382,7 @@ class ServerOpts(ctypes.Structure):
 
 class Request(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("algo", ctypes.c_int32), ("p", Problem),
-                ("t_arrival_ns", _i64)]
+                ("t_arrival_ns", _i64), ("ready_event", _vp)]
 
 
 class Result(ctypes.Structure):
@@ -430,10 +430,25 @@ class Server:
         h = _vp()
         check(lib().mg_server_create(ctypes.byref(o), ctypes.byref(h)))
         self._h = h
+        self._simulate = bool(simulate)
+        self._events = {}
 
-    def submit(self, A, B, C, alpha=1.0, beta=0.0, algo=NATIVE, t_arrival_ns=0) -> int:
-        return self.submit_request(Request(_dtype_code(C), algo, problem(A, B, C, alpha, beta),
-                                           t_arrival_ns))
+    def submit(self, A, B, C, alpha=1.0, beta=0.0, algo=NATIVE, t_arrival_ns=0,
+               stream=None) -> int:
+        """Queues one request.  Its kernels wait for an event recorded here on
+        ``stream`` (torch's current stream by default), so they run after
+        every write to A, B and C already enqueued there."""
+        import torch
+        ev = None
+        if not self._simulate:
+            ev = torch.cuda.Event()
+            ev.record(torch.cuda.current_stream() if stream is None else stream)
+        r = Request(_dtype_code(C), algo, problem(A, B, C, alpha, beta), t_arrival_ns,
+                    None if ev is None else ev.cuda_event)
+        t = self.submit_request(r)
+        if ev is not None:
+            self._events[t] = ev  # alive until the request is reported done
+        return t
 
     def submit_request(self, r: Request) -> int:
         t = ctypes.c_uint64()
@@ -444,11 +459,15 @@ class Server:
         """None while pending, else the result dict."""
         r = Result()
         rc = check(lib().mg_gemm_poll(self._h, ticket, ctypes.byref(r)))
-        return None if rc == PENDING else result_dict(r)
+        if rc == PENDING:
+            return None
+        self._events.pop(ticket, None)
+        return result_dict(r)
 
     def wait(self, ticket: int) -> dict:
         r = Result()
         check(lib().mg_gemm_wait(self._h, ticket, ctypes.byref(r)))
+        self._events.pop(ticket, None)
         return result_dict(r)
 
     def stats(self) -> dict:
@@ -457,8 +476,13 @@ class Server:
         return {f: getattr(s, f) for f, _ in ServerStats._fields_}
 
     def replay(self, reqs) -> "ctypes.Array":
-        """Open-loop replay of a ctypes Request array (arrival offsets in ns)."""
+        """Open-loop replay of a ctypes Request array (arrival offsets in ns).
+        Every write already enqueued on the device is finished first, so
+        requests without a ready_event see their operands complete."""
         n = len(reqs)
+        if not self._simulate:
+            import torch
+            torch.cuda.synchronize()
         res = (Result * max(1, n))()
         check(lib().mg_server_replay(self._h, n, reqs, res))
         return res

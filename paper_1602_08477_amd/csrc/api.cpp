@@ -190,7 +190,7 @@ extern "C" {
 
 const char *mg_last_error(void) { return g_err; }
 
-int mg_version(void) { return 10000; }
+int mg_version(void) { return 10100; }
 
 int mg_num_tile_cfgs(void) { return num_tile_cfgs(); }
 

@@ -145,9 +145,15 @@ void launch_batch(Server *S, Lane &L, int64_t batch_id) {
     if ((double)p.m * (double)p.n * (double)p.k >= kDirectMNK) direct.push_back(q);
     else (q->r.dtype == MG_F64 ? p64 : p32).push_back(p);
   }
+  // Order the batch after each request's producer (the caller's writes).
+  int rc = MG_OK;
+  for (Req *q : L.batch)
+    if (q->r.ready_event != nullptr &&
+        hipStreamWaitEvent(L.s, static_cast<hipEvent_t>(q->r.ready_event), 0) != hipSuccess)
+      rc = MG_ERR_HIP;
   const mg_tune_table *tab = S->has_table ? &S->table : nullptr;
   WorkList w64, w32;
-  int rc = build_worklist(MG_F64, (int64_t)p64.size(), p64.data(), tab, &w64);
+  if (rc == MG_OK) rc = build_worklist(MG_F64, (int64_t)p64.size(), p64.data(), tab, &w64);
   if (rc == MG_OK) rc = build_worklist(MG_F32, (int64_t)p32.size(), p32.data(), tab, &w32);
   const size_t o_t64 = 0;
   const size_t o_t32 = align256(o_t64 + w64.tiles.size());

@@ -197,8 +197,11 @@ def test_config2_sizes_sampled(mnk):
     C0 = dC.clone()
     mg.gemm(dA, dB, dC, 1.0, 1.0)
     torch.cuda.synchronize()
-    rows = np.unique(np.concatenate([[0, m - 1], synth.log_uniform_int(seed, 9, 40, 1, m - 1)]))
-    cols = np.unique(np.concatenate([[0, n - 1], synth.log_uniform_int(seed, 10, 40, 1, n - 1)]))
+    # log-uniform indices crowd the first tiles; uniform ones reach the last
+    rows = np.unique(np.concatenate([[0, m - 1], synth.log_uniform_int(seed, 9, 40, 1, m - 1),
+                                     (synth.uniform_unit(seed, 11, 40) * m).astype(np.int64)]))
+    cols = np.unique(np.concatenate([[0, n - 1], synth.log_uniform_int(seed, 10, 40, 1, n - 1),
+                                     (synth.uniform_unit(seed, 12, 40) * n).astype(np.int64)]))
     rt = torch.from_numpy(rows).cuda()
     ct = torch.from_numpy(cols).cuda()
     As = dA[rt].cpu().numpy()
@@ -207,6 +210,26 @@ def test_config2_sizes_sampled(mnk):
     got = dC[rt][:, ct].cpu().numpy()
     check_f64(got, As, Bs, Cs, 1.0, 1.0, f"config2 {mnk} sampled")
     assert torch.isfinite(dC).all()
+
+
+@pytest.mark.parametrize("mnk", [(4096, 4096, 4096), (8192, 1024, 4096), (8192, 8192, 8192)])
+def test_config2_full_output(mnk):
+    """Workload 2 at full size with the bench's work division: every output
+    element against the oracle (relative Frobenius error and the per-element
+    rounding bound), including the headline n = 8192."""
+    m, n, k = mnk
+    log(f"config2 full {mnk}")
+    seed = synth.config_seed(2)
+    dA = synth.matrix(seed, synth.STREAM_A, m, k, device="cuda")
+    dB = synth.matrix(seed, synth.STREAM_B, k, n, device="cuda")
+    dC = synth.matrix(seed, synth.STREAM_C, m, n, device="cuda")
+    C0 = dC.cpu().numpy()
+    mg.gemm(dA, dB, dC, 1.0, 1.0)
+    torch.cuda.synchronize()
+    A = dA.cpu().numpy()
+    B = dB.cpu().numpy()
+    del dA, dB
+    check_f64(dC.cpu().numpy(), A, B, C0, 1.0, 1.0, f"config2 {mnk} full")
 
 
 def test_metamorphic_transpose_bit_exact():

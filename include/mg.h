@@ -287,6 +287,21 @@ int mg_plan_destroy(mg_plan *plan);
  * after the launch has completed.  algo must be MG_NATIVE. */
 int mg_gemm_batched(int dtype, int algo, int64_t count, const mg_problem *probs, void *stream);
 
+/* mg_gemm_batched_noalloc: for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same problems, validation, tile classes (heuristic table) and
+ * results as mg_gemm_batched(dtype, MG_NATIVE, ...), bit for bit, but the
+ * work list goes to a static 8 MiB device array (one per GPU, held until the
+ * process ends; about 87 000 FP64 tiles) instead of library-allocated memory:
+ * the call makes no hipMalloc/hipFree and creates no event.  It copies the
+ * work list from host memory into that array on `stream` and launches the
+ * persistent kernel behind it.  Every call on a GPU shares that GPU's
+ * array: calls on one stream are ordered, but calls that overlap on one GPU
+ * (other streams, other threads, before an earlier launch has finished on
+ * another stream) race on it.  MG_ERR_INVALID_ARG (nothing enqueued) for a
+ * batch whose work list exceeds the array, with the size in the message. */
+int mg_gemm_batched_noalloc(int dtype, int64_t count, const mg_problem *probs, void *stream);
+
 /* ----------------------------------------------------------- serving --
  * A request loop with continuous batching.  Requests (each one GEMM of the
  * Section 4.2 form, operands already on the device) are submitted from any

@@ -297,6 +297,7 @@ def _bind_batched(L):
     L.mg_plan_get_stats.argtypes = [_vp, ctypes.POINTER(PlanStats)]
     L.mg_plan_destroy.argtypes = [_vp]
     L.mg_gemm_batched.argtypes = [_int, _int, _i64, ctypes.POINTER(Problem), _vp]
+    L.mg_gemm_batched_noalloc.argtypes = [_int, _i64, ctypes.POINTER(Problem), _vp]
 
 
 def problem(A, B, C, alpha=1.0, beta=0.0) -> Problem:
@@ -364,6 +365,13 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def gemm_batched_noalloc(probs, dtype: int = F64, stream=None):
+    """One-shot batched launch with no device allocation
+    (mg_gemm_batched_noalloc: work list in the library's static buffer)."""
+    arr, n = _problems(probs)
+    check(lib().mg_gemm_batched_noalloc(dtype, n, arr, _stream_handle(stream)))
 
 
 def gemm_batched(probs, dtype: int = F64, stream=None):

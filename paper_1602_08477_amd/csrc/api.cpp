@@ -505,6 +505,14 @@ int mg_plan_destroy(mg_plan *plan) {
   return MG_OK;
 }
 
+int mg_gemm_batched_noalloc(int dtype, int64_t count, const mg_problem *probs, void *stream) {
+  clear_error();
+  int rc = validate_batch(dtype, count, probs);
+  if (rc != MG_OK) return rc;
+  if (count == 0) return MG_OK;
+  return gemm_batched_noalloc(dtype, count, probs, static_cast<hipStream_t>(stream));
+}
+
 int mg_gemm_batched(int dtype, int algo, int64_t count, const mg_problem *probs, void *stream) {
   clear_error();
   if (algo != MG_NATIVE) {

@@ -42,6 +42,12 @@ int plan_launch(Plan *p, hipStream_t s, bool use_graph);
 void plan_destroy(Plan *p);
 const mg_plan_stats &plan_stats(const Plan *p);
 
+// Largest work list (bytes) of gemm_batched_noalloc: 8 MiB, about 87 000
+// FP64 tiles (96 bytes each).
+constexpr size_t kNoAllocWorklistBytes = (size_t)8 << 20;
+// One-shot batch whose work list goes to a static per-device buffer.
+int gemm_batched_noalloc(int dtype, int64_t count, const mg_problem *probs, hipStream_t s);
+
 // Times every tile class on every shape bucket and records the fastest.
 int autotune(int dtype, int reps, hipStream_t s, mg_tune_table *out);
 

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <type_traits>
 #include <vector>
@@ -782,6 +783,66 @@ void plan_destroy(Plan *p) {
 }
 
 const mg_plan_stats &plan_stats(const Plan *p) { return p->stats; }
+
+// ---------------------------------------------------------------------------
+// Batched launch without allocation: the work list lives in a fixed device
+// array (one copy per GPU, held until the process ends) instead of memory
+// the library allocates per call.
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocWorklistBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch` (the array's
+// name is only a host-side stand-in).  Resolved once per device, with that
+// device current.
+int scratch_address(void **out) {
+  int dev = 0;
+  MG_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device %d beyond the %d the static work-list buffer supports", dev, kMaxDevices);
+    return MG_ERR_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) {
+      set_error("hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                hipGetErrorString(e));
+      return MG_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return MG_OK;
+}
+
+}  // namespace
+
+int gemm_batched_noalloc(int dtype, int64_t count, const mg_problem *probs, hipStream_t s) {
+  // Host work list, reused by the calling thread (the copy below reads it
+  // from pageable memory, which HIP stages before the call returns).
+  thread_local WorkList wl;
+  int rc = build_worklist(dtype, count, probs, nullptr, &wl);
+  if (rc != MG_OK) return rc;
+  if (wl.ntiles == 0) return MG_OK;
+  if (wl.tiles.size() > kNoAllocWorklistBytes) {
+    set_error("batch needs a %zu-byte work list (%d tiles); the static buffer holds %zu bytes",
+              wl.tiles.size(), wl.ntiles, kNoAllocWorklistBytes);
+    return MG_ERR_INVALID_ARG;
+  }
+  void *ptr = nullptr;
+  if ((rc = scratch_address(&ptr)) != MG_OK) return rc;
+  int grid = 1;
+  if ((rc = grouped_grid(dtype, wl.ntiles, &grid, nullptr)) != MG_OK) return rc;
+  MG_HIP_TRY(hipMemcpyAsync(ptr, wl.tiles.data(), wl.tiles.size(), hipMemcpyHostToDevice, s));
+  return launch_worklist(dtype, ptr, wl.ntiles, grid, s);
+}
 
 }  // namespace mg
 

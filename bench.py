@@ -393,6 +393,64 @@ def bench_split(n, steps, warmup):
     return out
 
 
+def profile_batched():
+    """For counter runs: the 2000-problem batch (autotuned table) launched 3
+    times in FP64, then 3 times in FP32; these are the last 3 dispatches of
+    each grouped kernel."""
+    import torch
+    import paper_1602_08477_amd as mg
+    import synth
+    seed = synth.config_seed(4)
+    shapes = synth.batch_shapes(seed, 2000)
+    out = {}
+    for name, dt, code in (("f64", torch.float64, mg.F64), ("f32", torch.float32, mg.F32)):
+        offs = {"A": [0], "B": [0], "C": [0]}
+        for m_, n_, k_ in shapes:
+            for key, sz in (("A", m_ * k_), ("B", k_ * n_), ("C", m_ * n_)):
+                offs[key].append(offs[key][-1] + -(-int(sz) // 32) * 32)
+        flats = {key: synth.flat_uniform(seed, i, offs[key][-1], device="cuda").to(dt)
+                 for i, key in enumerate(("A", "B", "C"))}
+        probs = []
+        for i, (m_, n_, k_) in enumerate(shapes):
+            m_, n_, k_ = int(m_), int(n_), int(k_)
+            probs.append(mg.problem(
+                flats["A"][offs["A"][i]: offs["A"][i] + m_ * k_].view(m_, k_),
+                flats["B"][offs["B"][i]: offs["B"][i] + k_ * n_].view(k_, n_),
+                flats["C"][offs["C"][i]: offs["C"][i] + m_ * n_].view(m_, n_), 1.0, 1.0))
+        table = mg.autotune(code, reps=1)
+        plan = mg.Plan(code, probs, table)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            plan.launch(graph=False)
+        torch.cuda.synchronize()
+        out[name] = plan.stats()
+        plan.close()
+        del flats, probs
+        torch.cuda.empty_cache()
+    return out
+
+
+def profile_split(n=4096):
+    """For counter runs: native FP64, then split INT8 three times, then split
+    BF16 once, at n = 4096 on the exponent-spread workload (alpha=1, beta=0)."""
+    import torch
+    import paper_1602_08477_amd as mg
+    import synth
+    seed = synth.config_seed(3)
+    dA = synth.matrix(seed, synth.STREAM_A, n, n, kind="spread", device="cuda")
+    dB = synth.matrix(seed, synth.STREAM_B, n, n, kind="spread", device="cuda")
+    dC = torch.zeros(n, n, dtype=torch.float64, device="cuda")
+    mg.gemm(dA, dB, dC, 1.0, 0.0)
+    for algo, reps in ((mg.SPLIT_I8, 3), (mg.SPLIT_BF16, 1)):
+        s = mg.split_default_slices(algo)
+        ws = mg.split_workspace(algo, s, n, n, n)
+        for _ in range(reps):
+            mg.gemm_split(dA, dB, dC, 1.0, 0.0, algo=algo, slices=s, workspace=ws)
+        torch.cuda.synchronize()
+        del ws
+    return {"n": n}
+
+
 def batched_roofline_ms(shapes, esz, peak_tflops):
     """Sum over problems of max(FLOP / peak, compulsory bytes / 8 TB/s), ms."""
     m, n, k = (shapes[:, i].astype(np.float64) for i in range(3))
@@ -619,8 +677,8 @@ def serve_verify(mg, synth, pools, nmax, table, seconds=1.0, rate=2000.0):
     with mg.Server(n_streams=4, max_slots=256, max_batch=64, hbm_budget_bytes=64 << 30,
                    table=table) as srv:
         res = srv.replay(reqs)
-    pick = np.unique((synth.uniform_unit(seed, 13, max(200, count // 100)) * count)
-                     .astype(np.int64))
+    # a seeded sample of distinct requests: 1 % of them, at least 200
+    pick = np.sort(np.argsort(synth.uniform_unit(seed, 13, count))[:max(200, count // 100)])
     worst = {"native": 0.0, "split_i8": 0.0}
     checked = {"native": 0, "split_i8": 0}
     for i in pick:
@@ -650,6 +708,25 @@ def serve_verify(mg, synth, pools, nmax, table, seconds=1.0, rate=2000.0):
     return {"requests": count, "completed_ok": int(sum(r.status == 0 for r in res)),
             "checked_vs_oracle": checked,
             "rel_fro_err_max": {k: float(f"{v:.3e}") for k, v in worst.items()}}
+
+
+def profile_serving(rate=16000.0, seconds=2.0):
+    """For kernel traces: one open-loop trace of the serving mix at ``rate``
+    (default: past saturation) under a 64 GiB budget."""
+    import torch
+    import paper_1602_08477_amd as mg
+    import synth
+    nmax, pool_elems = 2048, 1 << 26
+    seed = synth.config_seed(5)
+    pools = (synth.flat_uniform(seed, 0, pool_elems, device="cuda"),
+             synth.flat_uniform(seed, 1, pool_elems, device="cuda"), pool_elems)
+    arena = torch.zeros(1 << 31, dtype=torch.float64, device="cuda")
+    table = mg.autotune(mg.F64, reps=2)
+    t0 = time.perf_counter()
+    out = serve_trace(mg, synth, synth.config_seed(5, 3), rate, seconds, pools, arena, nmax,
+                      64 << 30, table)
+    out["wall_s"] = round(time.perf_counter() - t0, 3)
+    return out
 
 
 def bench_serving(seconds, rate=2000.0):
@@ -751,7 +828,8 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--quick", action="store_true", help="headline only (for profiling)")
     ap.add_argument("--leg", choices=["sizes", "trans", "daxpy", "overhead", "split", "batched",
-                                      "serving"],
+                                      "serving", "profile_batched", "profile_split",
+                                      "profile_serving"],
                     default=None,
                     help="run only this secondary leg and print its record (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -779,7 +857,10 @@ def main():
               "daxpy": lambda: bench_daxpy(1 << 27, args.steps, args.warmup,
                                            cpu=not args.quick, small_n=not args.quick),
               "batched": lambda: bench_batched(max(3, args.steps)),
-              "serving": lambda: bench_serving(args.serve_seconds)}[args.leg]
+              "serving": lambda: bench_serving(args.serve_seconds),
+              "profile_batched": profile_batched,
+              "profile_split": profile_split,
+              "profile_serving": profile_serving}[args.leg]
         print(json.dumps({"leg": args.leg, "record": fn()}), flush=True)
         return
     n = args.n

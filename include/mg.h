@@ -264,8 +264,21 @@ int mg_tune_default(int dtype, mg_tune_table *out);
  * the largest class to give every workgroup slot of the persistent kernel
  * four tiles, so that classes compete on throughput in a full batch (reps
  * launches on `stream`, HIP events), and records the fastest.  Allocates and
- * frees its own scratch operands (about 0.4 GB for FP64); blocks until done. */
+ * frees its own scratch operands (about 0.4 GB for FP64); blocks until done.
+ * The work division is picked per architecture by measurement, as the paper
+ * picks it per architecture (Section 4.2.3).  If the environment variable
+ * MG_AUTOTUNE_CACHE names a file, this is mg_autotune_cached with that path. */
 int mg_autotune(int dtype, int reps, void *stream, mg_tune_table *out);
+
+/* mg_autotune through a persistent cache: a JSON file holding one table per
+ * (device architecture name, CU count, dtype, library version).  A table
+ * stored for the current device and dtype is returned without timing
+ * (*from_cache = 1); otherwise the buckets are timed and the file is
+ * rewritten with this table added or replaced (other entries kept; written
+ * to a temporary name and renamed).  cache_path NULL or "" means no cache.
+ * from_cache may be NULL.  MG_ERR_INVALID_ARG if the file cannot be written. */
+int mg_autotune_cached(int dtype, int reps, const char *cache_path, void *stream,
+                       mg_tune_table *out, int *from_cache);
 
 /* Builds a plan (host work list + device copy; blocks while uploading).
  * `table` may be NULL (heuristic).  *out must be released with
@@ -282,10 +295,18 @@ int mg_plan_get_stats(const mg_plan *plan, mg_plan_stats *out);
 /* Frees the plan.  The caller must make sure no launch of it is pending. */
 int mg_plan_destroy(mg_plan *plan);
 
-/* One-shot: plan (heuristic table) + direct launch on `stream`.  The plan's
- * device memory is released by a later library call once an event recorded
- * after the launch has completed.  algo must be MG_NATIVE. */
+/* One-shot: plan (heuristic table) + launch on `stream`.  algo must be
+ * MG_NATIVE.  The plan of each distinct problem set is kept (the last 8 sets
+ * per process, matched on device, dtype and every descriptor byte for byte)
+ * with its launch captured in a HIP graph: a call whose problem set repeats
+ * replays that graph instead of building and uploading a new work list (the
+ * list holds pointers, extents and scalars only, so each replay reads the
+ * operands' current contents).  An evicted plan's device memory is released
+ * by a later library call once its last launch has completed. */
 int mg_gemm_batched(int dtype, int algo, int64_t count, const mg_problem *probs, void *stream);
+/* Calls of mg_gemm_batched so far that replayed a kept plan (hits) and that
+ * built a new one (misses).  Either pointer may be NULL. */
+int mg_gemm_batched_cache_stats(int64_t *hits, int64_t *misses);
 
 /* mg_gemm_batched_noalloc: for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid

@@ -290,6 +290,8 @@ def _bind_batched(L):
     L.mg_tune_bucket.argtypes = [_i64, _i64, _i64]
     L.mg_tune_default.argtypes = [_int, ctypes.POINTER(TuneTable)]
     L.mg_autotune.argtypes = [_int, _int, _vp, ctypes.POINTER(TuneTable)]
+    L.mg_autotune_cached.argtypes = [_int, _int, ctypes.c_char_p, _vp, ctypes.POINTER(TuneTable),
+                                     ctypes.POINTER(_int)]
     L.mg_plan_create.argtypes = [_int, _i64, ctypes.POINTER(Problem), ctypes.POINTER(TuneTable),
                                  ctypes.POINTER(_vp)]
     L.mg_plan_launch.argtypes = [_vp, _vp]
@@ -297,6 +299,7 @@ def _bind_batched(L):
     L.mg_plan_get_stats.argtypes = [_vp, ctypes.POINTER(PlanStats)]
     L.mg_plan_destroy.argtypes = [_vp]
     L.mg_gemm_batched.argtypes = [_int, _int, _i64, ctypes.POINTER(Problem), _vp]
+    L.mg_gemm_batched_cache_stats.argtypes = [ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
     L.mg_gemm_batched_noalloc.argtypes = [_int, _i64, ctypes.POINTER(Problem), _vp]
 
 
@@ -327,9 +330,19 @@ def tune_default(dtype: int = F64) -> TuneTable:
     return t
 
 
-def autotune(dtype: int = F64, reps: int = 3, stream=None) -> TuneTable:
+def autotune(dtype: int = F64, reps: int = 3, stream=None, cache: str | None = None,
+             info: dict | None = None) -> TuneTable:
+    """mg_autotune, or mg_autotune_cached when ``cache`` names a JSON file;
+    ``info["from_cache"]`` tells whether the table came from it."""
     t = TuneTable()
-    check(lib().mg_autotune(dtype, reps, _stream_handle(stream), ctypes.byref(t)))
+    if cache is None:
+        check(lib().mg_autotune(dtype, reps, _stream_handle(stream), ctypes.byref(t)))
+        return t
+    hit = ctypes.c_int(0)
+    check(lib().mg_autotune_cached(dtype, reps, os.fsencode(cache), _stream_handle(stream),
+                                   ctypes.byref(t), ctypes.byref(hit)))
+    if info is not None:
+        info["from_cache"] = bool(hit.value)
     return t
 
 
@@ -375,9 +388,16 @@ def gemm_batched_noalloc(probs, dtype: int = F64, stream=None):
 
 
 def gemm_batched(probs, dtype: int = F64, stream=None):
-    """One-shot batched launch (mg_gemm_batched)."""
+    """One-shot batched launch (mg_gemm_batched; a repeated problem set
+    replays its kept graph)."""
     arr, n = _problems(probs)
     check(lib().mg_gemm_batched(dtype, NATIVE, n, arr, _stream_handle(stream)))
+
+
+def gemm_batched_cache_stats() -> dict:
+    h, m = _i64(), _i64()
+    check(lib().mg_gemm_batched_cache_stats(ctypes.byref(h), ctypes.byref(m)))
+    return {"hits": h.value, "misses": m.value}
 
 
 # ------------------------------------------------------------------ serving

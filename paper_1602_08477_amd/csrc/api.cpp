@@ -1,8 +1,10 @@
 // extern "C" boundary of libmg: argument validation, error reporting and
 // dispatch to the kernels.  Nothing is enqueued when validation fails.
+#include <cstdlib>
 #include <algorithm>
 #include <cstdarg>
 #include <cstring>
+#include <list>
 #include <mutex>
 #include <utility>
 #include <vector>
@@ -166,6 +168,39 @@ int validate_batch(int dtype, int64_t count, const mg_problem *probs) {
 // recorded after their launch has completed.
 std::mutex g_deferred_mu;
 std::vector<std::pair<Plan *, hipEvent_t>> g_deferred;
+
+// One-shot batches whose problem set repeats replay the graph of the plan
+// built the first time.  The last kPlanCacheSize distinct sets are kept,
+// matched on device, dtype and every descriptor byte for byte: the work list
+// holds only pointers, extents and scalars, so a replay reads the operands'
+// current contents.  An evicted plan is freed once its last launch has
+// completed (deferred like a one-shot plan).
+struct CachedBatch {
+  int device = 0, dtype = 0;
+  uint64_t hash = 0;
+  std::vector<mg_problem> probs;
+  Plan *plan = nullptr;
+  hipEvent_t last = nullptr;  // recorded after the latest launch of the plan
+};
+constexpr size_t kPlanCacheSize = 8;
+std::mutex g_cache_mu;
+std::list<CachedBatch> g_cache;  // most recently used first
+int64_t g_cache_hits = 0, g_cache_misses = 0;
+
+// Word-wise multiply-xor hash of the descriptors (a mg_problem is eleven
+// 8-byte fields, no padding).
+uint64_t hash_problems(int dtype, int64_t count, const mg_problem *p) {
+  static_assert(sizeof(mg_problem) == 11 * sizeof(uint64_t), "descriptor without padding");
+  uint64_t h = 0x9e3779b97f4a7c15ull ^ (uint64_t)dtype ^ ((uint64_t)count << 8);
+  const size_t words = (size_t)count * (sizeof(mg_problem) / sizeof(uint64_t));
+  for (size_t i = 0; i < words; ++i) {
+    uint64_t w;
+    std::memcpy(&w, reinterpret_cast<const unsigned char *>(p) + i * 8, 8);
+    h = (h ^ w) * 0xff51afd7ed558ccdull;
+    h ^= h >> 29;
+  }
+  return h;
+}
 
 void reap_deferred(bool wait) {
   std::lock_guard<std::mutex> lk(g_deferred_mu);
@@ -447,7 +482,19 @@ int mg_autotune(int dtype, int reps, void *stream, mg_tune_table *out) {
     set_error("bad dtype, reps or NULL table");
     return MG_ERR_INVALID_ARG;
   }
-  return autotune(dtype, reps, static_cast<hipStream_t>(stream), out);
+  return autotune_cached(dtype, reps, std::getenv("MG_AUTOTUNE_CACHE"),
+                         static_cast<hipStream_t>(stream), out, nullptr);
+}
+
+int mg_autotune_cached(int dtype, int reps, const char *cache_path, void *stream,
+                       mg_tune_table *out, int *from_cache) {
+  clear_error();
+  if (out == nullptr || esize(dtype) == 0 || reps < 1) {
+    set_error("bad dtype, reps or NULL table");
+    return MG_ERR_INVALID_ARG;
+  }
+  return autotune_cached(dtype, reps, cache_path, static_cast<hipStream_t>(stream), out,
+                         from_cache);
 }
 
 int mg_plan_create(int dtype, int64_t count, const mg_problem *probs, const mg_tune_table *table,
@@ -523,27 +570,63 @@ int mg_gemm_batched(int dtype, int algo, int64_t count, const mg_problem *probs,
   int rc = validate_batch(dtype, count, probs);
   if (rc != MG_OK) return rc;
   if (count == 0) return MG_OK;
-  Plan *p = nullptr;
-  rc = plan_create(dtype, count, probs, nullptr, &p);
-  if (rc != MG_OK) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  rc = plan_launch(p, s, false);
-  hipEvent_t ev = nullptr;
-  if (rc == MG_OK && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess &&
-      hipEventRecord(ev, s) == hipSuccess) {
-    std::lock_guard<std::mutex> lk(g_deferred_mu);
-    g_deferred.emplace_back(p, ev);
-    return MG_OK;
+  int dev = 0;
+  MG_HIP_TRY(hipGetDevice(&dev));
+  const uint64_t h = hash_problems(dtype, count, probs);
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (auto it = g_cache.begin(); it != g_cache.end(); ++it) {
+      if (it->device != dev || it->dtype != dtype || it->hash != h ||
+          (int64_t)it->probs.size() != count ||
+          std::memcmp(it->probs.data(), probs, (size_t)count * sizeof(mg_problem)) != 0)
+        continue;
+      g_cache.splice(g_cache.begin(), g_cache, it);  // most recently used
+      rc = plan_launch(it->plan, s, true);
+      if (rc == MG_OK) MG_HIP_TRY(hipEventRecord(it->last, s));
+      ++g_cache_hits;
+      return rc;
+    }
+    ++g_cache_misses;
   }
-  // could not defer: wait for the stream, then free
-  if (ev) (void)hipEventDestroy(ev);
-  (void)hipStreamSynchronize(s);
-  plan_destroy(p);
-  if (rc == MG_OK) {
+  CachedBatch e;
+  e.device = dev;
+  e.dtype = dtype;
+  e.hash = h;
+  e.probs.assign(probs, probs + count);
+  rc = plan_create(dtype, count, probs, nullptr, &e.plan);
+  if (rc != MG_OK) return rc;
+  rc = plan_launch(e.plan, s, true);  // captures the graph, then replays it
+  if (rc == MG_OK && (hipEventCreateWithFlags(&e.last, hipEventDisableTiming) != hipSuccess ||
+                      hipEventRecord(e.last, s) != hipSuccess)) {
     set_error("could not record completion event");
-    return MG_ERR_HIP;
+    rc = MG_ERR_HIP;
   }
-  return rc;
+  if (rc != MG_OK) {  // wait for anything enqueued, then free
+    (void)hipStreamSynchronize(s);
+    if (e.last) (void)hipEventDestroy(e.last);
+    plan_destroy(e.plan);
+    return rc;
+  }
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_cache.push_front(std::move(e));
+  while (g_cache.size() > kPlanCacheSize) {
+    CachedBatch &old = g_cache.back();
+    {
+      std::lock_guard<std::mutex> lk2(g_deferred_mu);
+      g_deferred.emplace_back(old.plan, old.last);
+    }
+    g_cache.pop_back();
+  }
+  return MG_OK;
+}
+
+int mg_gemm_batched_cache_stats(int64_t *hits, int64_t *misses) {
+  clear_error();
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  if (hits) *hits = g_cache_hits;
+  if (misses) *misses = g_cache_misses;
+  return MG_OK;
 }
 
 }  // extern "C"

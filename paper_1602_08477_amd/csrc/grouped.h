@@ -50,5 +50,8 @@ int gemm_batched_noalloc(int dtype, int64_t count, const mg_problem *probs, hipS
 
 // Times every tile class on every shape bucket and records the fastest.
 int autotune(int dtype, int reps, hipStream_t s, mg_tune_table *out);
+// autotune through the JSON cache at `path` (NULL or "": no cache).
+int autotune_cached(int dtype, int reps, const char *path, hipStream_t s, mg_tune_table *out,
+                    int *from_cache);
 
 }  // namespace mg

@@ -271,3 +271,59 @@ def test_large_problems_in_batch_contract(dt):
                 f"{int((diff > 0).sum())} of {m * n}")
         else:
             assert torch.equal(dflt, C), (m, n, k)
+
+
+def test_autotune_cache_roundtrip(tmp_path):
+    """The tuned table persists as JSON keyed by device, CU count, dtype and
+    library version: the first call times and writes, the second reads the
+    same table without timing; entries of other keys survive a rewrite."""
+    import json
+    path = str(tmp_path / "tune.json")
+    info = {}
+    t1 = mg.autotune(mg.F64, reps=1, cache=path, info=info)
+    assert info["from_cache"] is False
+    doc = json.load(open(path))
+    assert doc["format"] == "mg-autotune-1" and len(doc["tables"]) == 1
+    e = doc["tables"][0]
+    assert e["dtype"] == "f64" and e["classes"] == t1.to_list() and e["cus"] > 0
+    t2 = mg.autotune(mg.F64, reps=1, cache=path, info=info)
+    assert info["from_cache"] is True and t2.to_list() == t1.to_list()
+    t3 = mg.autotune(mg.F32, reps=1, cache=path, info=info)
+    assert info["from_cache"] is False
+    doc = json.load(open(path))
+    assert sorted(x["dtype"] for x in doc["tables"]) == ["f32", "f64"]
+    assert mg.autotune(mg.F32, reps=1, cache=path, info=info).to_list() == t3.to_list()
+    assert info["from_cache"] is True
+
+
+def test_one_shot_repeat_replays_graph_and_reads_current_data():
+    """mg_gemm_batched keeps the plan of each distinct problem set: a repeated
+    set replays its graph (a hit), and the replay reads the operands' current
+    contents; more than 8 other sets evict it (a miss again)."""
+    shapes = [tuple(int(x) for x in s) for s in synth.batch_shapes(93, 50, 1, 300)]
+    views, flats, probs = make_batch(93, shapes, beta=0.0)
+    s0 = mg.gemm_batched_cache_stats()
+    mg.gemm_batched(probs)
+    torch.cuda.synchronize()
+    first = [C.clone() for _, _, C in views]
+    for (A, B, _), got in zip(views, first):
+        check_problem(A, B, torch.zeros_like(got), got, 1.0, 0.0)
+    flats["A"].mul_(2.0)  # new operand values behind the same descriptors
+    mg.gemm_batched(probs)
+    torch.cuda.synchronize()
+    s1 = mg.gemm_batched_cache_stats()
+    assert s1["hits"] == s0["hits"] + 1 and s1["misses"] == s0["misses"] + 1
+    assert all(torch.equal(C, 2.0 * f) for (_, _, C), f in zip(views, first))
+    others = []
+    for i in range(9):
+        v, f, p = make_batch(94 + i, [(40 + i, 30, 20)], beta=0.0)
+        mg.gemm_batched(p)
+        others.append((v, f))
+    mg.gemm_batched(probs)
+    torch.cuda.synchronize()
+    s2 = mg.gemm_batched_cache_stats()
+    assert s2["misses"] == s1["misses"] + 10 and s2["hits"] == s1["hits"]
+    assert all(torch.equal(C, 2.0 * f) for (_, _, C), f in zip(views, first))
+    for v, _ in others:
+        A, B, C = v[0]
+        check_problem(A, B, torch.zeros_like(C), C, 1.0, 0.0)

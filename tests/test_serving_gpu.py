@@ -266,9 +266,9 @@ def test_config5_trace_alone_equals_mix_and_oracle():
             g = got.cpu().numpy()
         else:
             r = np.unique(np.concatenate([[0, n - 1],
-                                          (synth.uniform_unit(seed + i, 14, 14) * n).astype(int)]))
+                                          (synth.uniform_unit(seed + int(i), 14, 14) * n).astype(int)]))
             cidx = np.unique(np.concatenate([[0, n - 1],
-                                             (synth.uniform_unit(seed + i, 15, 14) * n).astype(int)]))
+                                             (synth.uniform_unit(seed + int(i), 15, 14) * n).astype(int)]))
             rt, ct = torch.from_numpy(r).cuda(), torch.from_numpy(cidx).cuda()
             ref = oracle.dgemm(1.0, a[rt].cpu().numpy(), b[:, ct].cpu().numpy(), 1.0,
                                c0[rt][:, ct].cpu().numpy())

@@ -371,12 +371,15 @@ __device__ __forceinline__ GTileRec<T> gd_record(const GTileRec<T> *tiles, int w
 // NS-1 k-steps ahead, and remembers how many DMA instructions each issued
 // but unconsumed step has (at most two with a 3-stage ring).
 // Tile of workgroup b in dealing round r: rounds alternate direction
-// (b, then G-1-b), so with the list in decreasing cost every workgroup gets
-// a fair share of the expensive and of the cheap tiles.  Past the list:
-// ntiles.
+// (b', then G-1-b'), so with the list in decreasing cost every workgroup gets
+// a fair share of the expensive and of the cheap tiles.  b' numbers the
+// workgroups XCD by XCD (the dispatcher places workgroup b on XCD b % 8), so
+// each XCD takes a contiguous run of every round: the tiles of one problem,
+// adjacent in the list, then share one L2.  Past the list: ntiles.
 __device__ __forceinline__ int gd_deal(int r, int b, int G, int ntiles) {
   if ((int64_t)r * G >= ntiles) return ntiles;
-  const int w = r * G + ((r & 1) ? G - 1 - b : b);
+  const int bx = xcd_remap(b, G);
+  const int w = r * G + ((r & 1) ? G - 1 - bx : bx);
   return w < ntiles ? w : ntiles;
 }
 

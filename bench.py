@@ -390,6 +390,25 @@ def bench_split(n, steps, warmup):
     out["split_faster_than_native"] = out["i8"]["ms"] < out["native_f64"]["ms"]
     del dA, dB
     torch.cuda.empty_cache()
+    # smaller sizes (the serving mix's range): split INT8 against native FP64
+    sweep = []
+    for sn in (128, 256, 512, 1024, 2048):
+        sA = synth.matrix(seed, synth.STREAM_A, sn, sn, kind="spread", device="cuda")
+        sB = synth.matrix(seed, synth.STREAM_B, sn, sn, kind="spread", device="cuda")
+        sC = torch.zeros(sn, sn, dtype=torch.float64, device="cuda")
+        ss = mg.split_default_slices(mg.SPLIT_I8)
+        ws = mg.split_workspace(mg.SPLIT_I8, ss, sn, sn, sn)
+        per_n, per_s = time_interleaved(
+            [lambda: mg.gemm(sA, sB, sC, 1.0, 0.0),
+             lambda: mg.gemm_split(sA, sB, sC, 1.0, 0.0, algo=mg.SPLIT_I8, slices=ss,
+                                   workspace=ws)], steps, warmup, stream)
+        ms_n, ms_s = float(np.median(per_n)), float(np.median(per_s))
+        sweep.append({"n": sn, "native_ms": round(ms_n, 4), "i8_ms": round(ms_s, 4),
+                      "native_tflops": round(2.0 * sn ** 3 / ms_n / 1e9, 2),
+                      "i8_tflops_fp64_equiv": round(2.0 * sn ** 3 / ms_s / 1e9, 2)})
+        del sA, sB, sC, ws
+    out["sizes"] = sweep
+    torch.cuda.empty_cache()
     return out
 
 

@@ -156,6 +156,9 @@ int mg_daxpy(int64_t n, double alpha, const double *x, int64_t incx, double *y, 
  *   A slices at a_off: [s][mp][kp] row-major elements (INT8, or BF16 bits)
  *   B slices at b_off: [s][np][kp], i.e. slice t of B transposed (k fastest)
  *   padding (rows >= m, columns >= n, k >= k) is zero.
+ *   p_off: the product kernels' scratch up to total_bytes: FP64 partial sums
+ *   [mp][np], or, for shapes the pair-parallel division serves, its INT32
+ *   partial diagonal sums (larger; total_bytes accounts for it).
  */
 typedef struct mg_split_layout {
   int64_t mp, np, kp, elem_bytes;
@@ -188,7 +191,12 @@ int mg_gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double 
  * 2: 128x256 on 8 (ring of 3), 3: 256x128 on 4 (ring of 3), 4: 256x256 on
  * 16 (ring of 2), 5: 128x256 on 8 (ring of 2); with 64-byte k stages:
  * 6: 256x256 on 8 (ring of 4), 7: 256x256 on 16 (ring of 4), 8: 128x256 on 8
- * (ring of 6).  mg_gemm_split picks by size;
+ * (ring of 6); 9-14 further tile and ring shapes; 15: pair-parallel, for
+ * shapes with fewer than 512 tiles of 128x128 (mp/128 * np/128 < 512): the
+ * slice pairs are cut into groups, each workgroup sums one group's pairs for
+ * one 128x128 tile and writes exact INT32 partial diagonal sums, and a second
+ * kernel adds them and folds them into FP64 as the other divisions do
+ * (MG_ERR_INVALID_ARG on larger shapes).  mg_gemm_split picks by size;
  * mg_gemm_split_cfg takes cfg explicitly (-1 = pick).  MG_ERR_INVALID_ARG for
  * an unknown cfg. */
 int mg_split_num_cfgs(void);

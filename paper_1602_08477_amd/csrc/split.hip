@@ -233,6 +233,7 @@ struct SplitArgs {
   const unsigned char *As, *Bs;
   const int *E, *F;
   double *P;  // FP64 partial sums [mp][np]
+  int32_t *Q; // pair-parallel division: INT32 partial diagonal sums (in P's region)
   double *C;
   int64_t ldc;
   int m, n, mp, np;
@@ -637,6 +638,235 @@ split_gemm_dma_kernel(SplitArgs a, int tiles_m, int tiles_n) {
                                        n0 + wn0 + l16);
 }
 
+// ---------------------------------------------------------------------------
+// Pair-parallel division (for grids with fewer than two 128x128 tiles per
+// CU).  The s(s+1)/2 slice pairs, in the order the fused kernels walk them
+// (d = 2..s+1, then p), are cut into G contiguous groups of near-equal
+// size; workgroup (group g, tile) sums only its group's pairs and writes, for
+// every diagonal d the group touches and every k segment, the exact INT32
+// partial sum of P_d to a slot of Q (row-major [mp][np] per slot).  A second
+// kernel adds a diagonal's partial sums (exact integers: the sum is P_d
+// itself) and folds P_d 2^(-b d) into FP64 in increasing d with the same
+// operations as the fused kernels' folds and epilogue, so the result is the
+// same bit for bit; only the order in which the integer parts are formed
+// differs, and integer addition is exact.
+constexpr int kMaxPairGroups = 32;
+
+struct PairGroups {
+  int G, slots, nseg;
+  int16_t pb[kMaxPairGroups], pe[kMaxPairGroups];   // pair range [pb, pe) of group g
+  int16_t dlo[kMaxPairGroups], dhi[kMaxPairGroups]; // diagonals it touches
+  int16_t base[kMaxPairGroups];                     // its first slot (for dlo)
+};
+
+// Pair index -> (d, p) in walk order, by stepping from (2, 1).
+__device__ __forceinline__ void pair_of(int pi, int s, int &d, int &p) {
+  d = 2;
+  p = 1;
+  for (int i = 0; i < pi; ++i) {
+    if (++p > pmax_of(d, s)) {
+      ++d;
+      p = max(1, d - s);
+    }
+  }
+}
+
+template <int ALGO, int MINB>
+__global__ __launch_bounds__(256, MINB) void split_pairs_kernel(SplitArgs a, PairGroups pg,
+                                                                 int tiles_m, int tiles_n) {
+  typedef SplitMma<ALGO> M;
+  typedef typename M::acc_t Acc;
+  typedef SplitShape<2, 2, 4, 4> S;  // 128x128 tile, 4 wavefronts of 64x64
+  constexpr int FMW = 4, FNW = 4;
+  constexpr int BM = S::BM, BN = S::BN, STAGE = S::STAGE;
+  constexpr int CPR = kStageBytes / 16;
+  extern __shared__ __align__(16) unsigned char lds[];
+
+  const int tiles = tiles_m * tiles_n;
+  const int grp = blockIdx.x / tiles, tb = blockIdx.x % tiles;
+  int tm, tn;
+  grouped_tile(tb, tiles_m, tiles_n, 8, tm, tn);
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave / 2) * 16 * FMW, wn0 = (wave % 2) * 16 * FNW;
+  const int g = lane >> 4, l16 = lane & 15;
+
+  const int64_t a_slice = (int64_t)a.mp * a.kp_bytes, b_slice = (int64_t)a.np * a.kp_bytes;
+  int arow[S::NA], acol[S::NA], brow[S::NB], bcol[S::NB];
+#pragma unroll
+  for (int u = 0; u < S::NA; ++u) {
+    const int q = tid + S::THREADS * u;
+    arow[u] = q / CPR;
+    acol[u] = (q % CPR) * 16;
+  }
+#pragma unroll
+  for (int u = 0; u < S::NB; ++u) {
+    const int q = tid + S::THREADS * u;
+    brow[u] = q / CPR;
+    bcol[u] = (q % CPR) * 16;
+  }
+  const unsigned char *abase = a.As + (int64_t)m0 * a.kp_bytes;
+  const unsigned char *bbase = a.Bs + (int64_t)n0 * a.kp_bytes;
+
+  // the group's walk: for each segment, pairs pb .. pe-1, each over the
+  // segment's stages
+  struct GStep {
+    int seg, pi, d, p, st;
+  };
+  const int pb = pg.pb[grp], pe = pg.pe[grp];
+  GStep first;
+  first.seg = 0;
+  first.pi = pb;
+  first.st = 0;
+  pair_of(pb, a.s, first.d, first.p);
+  auto advance_g = [&](GStep &x) {
+    if (++x.st < seg_len(x.seg, a)) return;
+    x.st = 0;
+    if (++x.pi < pe) {
+      if (++x.p > pmax_of(x.d, a.s)) {
+        ++x.d;
+        x.p = max(1, x.d - a.s);
+      }
+      return;
+    }
+    ++x.seg;
+    x.pi = pb;
+    x.d = first.d;
+    x.p = first.p;
+  };
+
+  i4v ra[S::NA], rb[S::NB];
+  auto load = [&](const GStep &x) {
+    const int64_t koff = (int64_t)(x.seg * a.seg_stages + x.st) * kStageBytes;
+    const unsigned char *pa = abase + (x.p - 1) * a_slice + koff;
+    const unsigned char *pbp = bbase + (x.d - x.p - 1) * b_slice + koff;
+#pragma unroll
+    for (int u = 0; u < S::NA; ++u)
+      ra[u] = *reinterpret_cast<const i4v *>(pa + arow[u] * a.kp_bytes + acol[u]);
+#pragma unroll
+    for (int u = 0; u < S::NB; ++u)
+      rb[u] = *reinterpret_cast<const i4v *>(pbp + brow[u] * a.kp_bytes + bcol[u]);
+  };
+  auto store = [&](int stage) {
+    unsigned char *As = lds + stage * STAGE;
+    unsigned char *Bs = As + BM * kPitch;
+#pragma unroll
+    for (int u = 0; u < S::NA; ++u)
+      *reinterpret_cast<i4v *>(As + arow[u] * kPitch + acol[u]) = ra[u];
+#pragma unroll
+    for (int u = 0; u < S::NB; ++u)
+      *reinterpret_cast<i4v *>(Bs + brow[u] * kPitch + bcol[u]) = rb[u];
+  };
+
+  Acc acc[FMW][FNW];
+  i4v dacc[FMW][FNW];
+#pragma unroll
+  for (int i = 0; i < FMW; ++i)
+#pragma unroll
+    for (int j = 0; j < FNW; ++j) {
+      acc[i][j] = Acc{};
+      dacc[i][j] = i4v{};
+    }
+  const int64_t plane = (int64_t)a.mp * a.np;
+  const int row0 = m0 + wm0 + 4 * g, col0 = n0 + wn0 + l16;
+
+  const int T = (pe - pb) * a.total_stages;
+  GStep cur = first;
+  load(cur);
+  store(0);
+  __syncthreads();
+  for (int t = 0; t < T; ++t) {
+    GStep nxt = cur;
+    advance_g(nxt);
+    if (t + 1 < T) load(nxt);
+    const unsigned char *As = lds + (t & 1) * STAGE;
+    const unsigned char *Bs = As + BM * kPitch;
+#pragma unroll
+    for (int h = 0; h < kStageBytes / 64; ++h) {
+      i4v fa[FMW], fb[FNW];
+#pragma unroll
+      for (int i = 0; i < FMW; ++i)
+        fa[i] = *reinterpret_cast<const i4v *>(As + (wm0 + 16 * i + l16) * kPitch + h * 64 + g * 16);
+#pragma unroll
+      for (int j = 0; j < FNW; ++j)
+        fb[j] = *reinterpret_cast<const i4v *>(Bs + (wn0 + 16 * j + l16) * kPitch + h * 64 + g * 16);
+#pragma unroll
+      for (int i = 0; i < FMW; ++i)
+#pragma unroll
+        for (int j = 0; j < FNW; ++j) acc[i][j] = M::mma(fa[i], fb[j], acc[i][j]);
+    }
+    const bool seg_last = cur.st + 1 == seg_len(cur.seg, a);
+    if (M::CHUNK_STAGES > 0 && ((cur.st + 1) % (M::CHUNK_STAGES > 0 ? M::CHUNK_STAGES : 1) == 0 ||
+                                seg_last)) {
+#pragma unroll
+      for (int i = 0; i < FMW; ++i)
+#pragma unroll
+        for (int j = 0; j < FNW; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            dacc[i][j][r] += (int)acc[i][j][r];
+            acc[i][j][r] = 0;
+          }
+    }
+    // last pair of its diagonal within this group (and segment): write the
+    // group's part of P_d for this segment, then start the next diagonal
+    const bool diag_end = seg_last && (cur.pi + 1 == pe || cur.p == pmax_of(cur.d, a.s));
+    if (diag_end) {
+      int32_t *q = a.Q + ((int64_t)cur.seg * pg.slots + pg.base[grp] + (cur.d - pg.dlo[grp])) * plane;
+#pragma unroll
+      for (int i = 0; i < FMW; ++i)
+#pragma unroll
+        for (int j = 0; j < FNW; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int v = M::CHUNK_STAGES > 0 ? dacc[i][j][r] : (int)acc[i][j][r];
+            q[(int64_t)(row0 + 16 * i + r) * a.np + col0 + 16 * j] = v;
+            dacc[i][j][r] = 0;
+            if (M::CHUNK_STAGES == 0) acc[i][j][r] = 0;
+          }
+    }
+    if (t + 1 < T) store((t + 1) & 1);
+    __syncthreads();
+    cur = nxt;
+  }
+}
+
+// C <- alpha * 2^(E_i+F_j) * sum_d P_d 2^(-b d) + beta * C from the partial
+// diagonal sums of split_pairs_kernel: per output, P_d of each segment is the
+// exact sum of the groups' parts, folded in the fused kernels' order
+// (segments, then increasing d; the first fold starts from 0) with the same
+// fused multiply-adds and the same epilogue arithmetic.
+__global__ void split_fold_kernel(SplitArgs a, PairGroups pg) {
+  const int64_t total = (int64_t)a.m * a.n;
+  const int64_t plane = (int64_t)a.mp * a.np;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int row = (int)(e / a.n), col = (int)(e % a.n);
+    const int64_t at = (int64_t)row * a.np + col;
+    double part = 0.0, fin = 0.0;
+    bool first = true;
+    for (int seg = 0; seg < pg.nseg; ++seg)
+      for (int d = 2; d <= a.s + 1; ++d) {
+        long long v = 0;
+        for (int gq = 0; gq < pg.G; ++gq)
+          if (pg.dlo[gq] <= d && d <= pg.dhi[gq])
+            v += a.Q[((int64_t)seg * pg.slots + pg.base[gq] + (d - pg.dlo[gq])) * plane + at];
+        const double sc = ldexp(1.0, -a.bits * d);
+        if (seg == pg.nseg - 1 && d == a.s + 1) {
+          fin = fma((double)(int)v, sc, first ? 0.0 : part);
+        } else {
+          part = fma((double)(int)v, sc, first ? 0.0 : part);
+          first = false;
+        }
+      }
+    const double prod = ldexp(fin, a.E[row] + a.F[col]);
+    double *c = a.C + (int64_t)row * a.ldc + col;
+    double o = __dmul_rn(a.alpha, prod);
+    if (a.beta != 0.0) o = __dadd_rn(o, __dmul_rn(a.beta, *c));
+    *c = o;
+  }
+}
+
 template <typename K>
 int ensure_lds(K kern, size_t bytes) {
   MG_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -683,6 +913,24 @@ int launch_split_dma(int algo, const SplitArgs &a, const SplitLayout &L, hipStre
              : launch_split_dma_t<MG_SPLIT_I8, WGM, WGN, FMW, FNW, NS, SB>(a, L, s);
 }
 
+template <int ALGO>
+int launch_pairs(const SplitArgs &a, const PairGroups &pg, const SplitLayout &L, hipStream_t s) {
+  typedef SplitShape<2, 2, 4, 4> S;
+  constexpr int MINB = ALGO == MG_SPLIT_I8 ? 2 : 1;  // as the fused 128x128 register tile
+  auto kern = split_pairs_kernel<ALGO, MINB>;
+  static int once = ensure_lds(kern, S::LDS_BYTES);
+  if (once != MG_OK) return once;
+  const int tiles_m = (int)(L.mp / S::BM), tiles_n = (int)(L.np / S::BN);
+  hipLaunchKernelGGL(kern, dim3((unsigned)(tiles_m * tiles_n * pg.G)), dim3(S::THREADS),
+                     S::LDS_BYTES, s, a, pg, tiles_m, tiles_n);
+  MG_HIP_TRY(hipGetLastError());
+  const int64_t total = (int64_t)a.m * a.n;
+  const int blocks = (int)std::min<int64_t>(ceil_div(total, 256), 4096);
+  hipLaunchKernelGGL(split_fold_kernel, dim3(blocks), dim3(256), 0, s, a, pg);
+  MG_HIP_TRY(hipGetLastError());
+  return MG_OK;
+}
+
 template <int WGM, int WGN, int FMW, int FNW>
 int launch_split(int algo, const SplitArgs &a, const SplitLayout &L, hipStream_t s) {
   return algo == MG_SPLIT_BF16 ? launch_split_t<MG_SPLIT_BF16, WGM, WGN, FMW, FNW>(a, L, s)
@@ -694,6 +942,64 @@ int launch_split(int algo, const SplitArgs &a, const SplitLayout &L, hipStream_t
 int split_default_slices(int algo) { return algo == MG_SPLIT_BF16 ? 6 : 7; }
 
 int split_bits(int algo) { return algo == MG_SPLIT_BF16 ? 8 : 7; }
+
+namespace {
+
+// Longest k segment (in 128-byte stages) whose diagonal sums stay exact in
+// INT32: slices * kseg * (2^b - 1)^2 < 2^31; BF16 segments hold whole
+// 256-long FP32 chunks.  0 if even one stage would overflow.
+int64_t seg_stages_of(int algo, int slices) {
+  const int bits = split_bits(algo);
+  const int64_t smax = (int64_t)((1u << bits) - 1) * ((1u << bits) - 1);
+  const int64_t kseg = ((int64_t)INT32_MAX / (slices * smax));
+  const int64_t per_stage = kStageBytes / (algo == MG_SPLIT_BF16 ? 2 : 1);
+  int64_t st = kseg / per_stage;
+  if (algo == MG_SPLIT_BF16) st -= st % SplitMma<MG_SPLIT_BF16>::CHUNK_STAGES;
+  return st;
+}
+
+// Tiles of 128x128 below which the pair-parallel division is the default
+// (two per CU on the 256 CUs of MI355X), and the workgroups it aims for.
+constexpr int64_t kPairTilesBelow = 512;
+constexpr int64_t kPairTargetWgs = 512;
+
+bool pairs_eligible(int64_t mp, int64_t np) { return (mp / 128) * (np / 128) < kPairTilesBelow; }
+
+// Pair groups of the pair-parallel division for a padded shape: G groups of
+// near-equal contiguous pair ranges, enough to give about kPairTargetWgs
+// workgroups; their diagonal spans, slot bases and the segment count.
+PairGroups pair_groups(int algo, int slices, int64_t mp, int64_t np, int64_t kp) {
+  PairGroups pg{};
+  const int P = slices * (slices + 1) / 2;
+  const int64_t tiles = (mp / 128) * (np / 128);
+  pg.G = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)P, (int64_t)kMaxPairGroups,
+                                                      ceil_div(kPairTargetWgs, tiles)}));
+  auto d_of = [&](int pi) {
+    int d = 2, p = 1;
+    for (int i = 0; i < pi; ++i)
+      if (++p > std::min(slices, d - 1)) {
+        ++d;
+        p = std::max(1, d - slices);
+      }
+    return d;
+  };
+  int slots = 0;
+  for (int g = 0; g < pg.G; ++g) {
+    pg.pb[g] = (int16_t)((int64_t)g * P / pg.G);
+    pg.pe[g] = (int16_t)((int64_t)(g + 1) * P / pg.G);
+    pg.dlo[g] = (int16_t)d_of(pg.pb[g]);
+    pg.dhi[g] = (int16_t)d_of(pg.pe[g] - 1);
+    pg.base[g] = (int16_t)slots;
+    slots += pg.dhi[g] - pg.dlo[g] + 1;
+  }
+  pg.slots = slots;
+  const int64_t total_stages = kp * (algo == MG_SPLIT_BF16 ? 2 : 1) / kStageBytes;
+  const int64_t seg = std::max<int64_t>(1, std::min(seg_stages_of(algo, slices), total_stages));
+  pg.nseg = (int)ceil_div(total_stages, seg);
+  return pg;
+}
+
+}  // namespace
 
 int split_layout(int algo, int slices, int64_t m, int64_t n, int64_t k, SplitLayout *L) {
   if (algo != MG_SPLIT_I8 && algo != MG_SPLIT_BF16) {
@@ -722,7 +1028,14 @@ int split_layout(int algo, int slices, int64_t m, int64_t n, int64_t k, SplitLay
   L->b_off = off;
   off = round_up(off + slices * L->np * L->kp * L->elem_bytes, 256);
   L->p_off = off;
-  off = round_up(off + 8 * L->mp * L->np, 256);
+  // FP64 partial sums of the fused divisions, or (shapes the pair-parallel
+  // division serves) the INT32 partial diagonal sums of its groups
+  int64_t pbytes = 8 * L->mp * L->np;
+  if (pairs_eligible(L->mp, L->np)) {
+    const PairGroups pg = pair_groups(algo, slices, L->mp, L->np, L->kp);
+    pbytes = std::max<int64_t>(pbytes, (int64_t)pg.nseg * pg.slots * L->mp * L->np * 4);
+  }
+  off = round_up(off + pbytes, 256);
   L->total = off;
   return MG_OK;
 }
@@ -771,12 +1084,16 @@ int split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, const d
   return MG_OK;
 }
 
-int split_num_cfgs() { return 15; }
+int split_num_cfgs() { return 16; }
 
 // Product-kernel work division (measured on MI355X at n = 4096): the 256x256
 // direct-to-LDS tile once every CU gets one, then the 128x256 one, else the
 // register-staged 128x128 tile.
 int split_pick_cfg(int algo, int64_t mp, int64_t np) {
+  // Below two 128x128 tiles per CU the pair-parallel division (15): the
+  // fused divisions would give too few workgroups, each walking all the
+  // slice pairs as one chain of dependent loads.
+  if (pairs_eligible(mp, np)) return 15;
   // INT8: the 16-wave 256x256 tile once it fills the chip.  BF16 keeps its
   // FP32 chunk accumulators in registers: 128x128 tiles on 8 waves, two
   // workgroups per CU.
@@ -794,6 +1111,7 @@ int split_multiply(int algo, int slices, int64_t m, int64_t n, int64_t k, double
   unsigned char *w = static_cast<unsigned char *>(ws);
   SplitArgs a;
   a.P = reinterpret_cast<double *>(w + L.p_off);
+  a.Q = nullptr;
   a.As = w + L.a_off;
   a.Bs = w + L.b_off;
   a.E = reinterpret_cast<const int *>(w + L.e_off);
@@ -839,6 +1157,17 @@ int split_multiply(int algo, int slices, int64_t m, int64_t n, int64_t k, double
     case 12: return launch_split_dma<2, 4, 4, 2, 2, 128>(algo, a, L, s);  // 128x128, 8 waves, 2 x 128 B
     case 13: return launch_split_dma<2, 2, 4, 4, 2, 128>(algo, a, L, s);  // 128x128, 4 waves, 2 x 128 B
     case 14: return launch_split_dma<2, 4, 4, 2, 3, 128>(algo, a, L, s);  // 128x128, 8 waves, 3 x 128 B
+    case 15: {  // pair-parallel: groups of slice pairs x 128x128 tiles, then the fold
+      if (!pairs_eligible(L.mp, L.np)) {
+        set_error("split work division 15 serves shapes with fewer than %lld tiles of 128x128",
+                  (long long)kPairTilesBelow);
+        return MG_ERR_INVALID_ARG;
+      }
+      const PairGroups pg = pair_groups(algo, slices, L.mp, L.np, L.kp);
+      a.Q = reinterpret_cast<int32_t *>(w + L.p_off);
+      return algo == MG_SPLIT_BF16 ? launch_pairs<MG_SPLIT_BF16>(a, pg, L, s)
+                                   : launch_pairs<MG_SPLIT_I8>(a, pg, L, s);
+    }
   }
   set_error("unknown split cfg %d", cfg);
   return MG_ERR_INVALID_ARG;

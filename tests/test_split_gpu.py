@@ -262,3 +262,31 @@ def test_split_row_permutation_and_power_of_two_scaling(kind):
     assert np.array_equal(go(np.ascontiguousarray(A[perm])), base[perm])
     t = np.arange(m) % 7 - 3  # per-row power-of-two scale factors
     assert np.array_equal(go(A * np.ldexp(1.0, t)[:, None]), base * np.ldexp(1.0, t)[:, None])
+
+
+@pytest.mark.parametrize("kind", ["i8", "bf16"])
+@pytest.mark.parametrize("shape,s", [((1792, 1700, 256), None), ((700, 650, 300), None),
+                                     ((100, 90, 20000), None), ((64, 80, 96), 1),
+                                     ((64, 80, 96), 2), ((200, 150, 130), 16)])
+def test_pair_parallel_matches_fused(kind, shape, s):
+    """The pair-parallel division (15: groups of slice pairs x 128x128 tiles,
+    then the fold) gives the fused register-staged division's bits, across
+    group counts (2 to 28 groups), several k segments (k = 20000) and slice
+    counts 1, 2 and 16."""
+    m, n, k = shape
+    algo = ALGOS[kind]
+    default = s is None
+    s = s or mg.split_default_slices(algo)
+    A, B, C = spread(80 + m % 97, m, n, k)
+    dA, dB = to_dev(A), to_dev(B)
+    out = []
+    for cfg in (0, 15):
+        dC = to_dev(C)
+        mg.gemm_split(dA, dB, dC, 1.25, 0.75, algo=algo, slices=s, cfg=cfg)
+        torch.cuda.synchronize()
+        out.append(dC.cpu().numpy())
+    log(f"pairs vs fused {kind} s={s} {shape}: equal={np.array_equal(out[0], out[1])}")
+    assert np.array_equal(out[0], out[1])
+    if default and m * n * k <= 100 * 90 * 20000:
+        ref = oracle.dgemm(1.25, A, B, 0.75, C)
+        assert oracle.rel_fro_err(out[1], ref) <= 1e-12

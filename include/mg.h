@@ -192,7 +192,7 @@ int mg_gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double 
  * 16 (ring of 2), 5: 128x256 on 8 (ring of 2); with 64-byte k stages:
  * 6: 256x256 on 8 (ring of 4), 7: 256x256 on 16 (ring of 4), 8: 128x256 on 8
  * (ring of 6); 9-14 further tile and ring shapes; 15: pair-parallel, for
- * shapes with fewer than 512 tiles of 128x128 (mp/128 * np/128 < 512): the
+ * shapes with fewer than 256 tiles of 128x128 (mp/128 * np/128 < 256): the
  * slice pairs are cut into groups, each workgroup sums one group's pairs for
  * one 128x128 tile and writes exact INT32 partial diagonal sums, and a second
  * kernel adds them and folds them into FP64 as the other divisions do

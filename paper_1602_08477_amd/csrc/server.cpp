@@ -187,10 +187,12 @@ void launch_batch(Server *S, Lane &L, int64_t batch_id) {
     if (q->r.algo == MG_NATIVE) continue;
     const mg_problem &p = q->r.p;
     const int sl = split_default_slices(q->r.algo);
+    // the batches share the device: the fused divisions (same bits as the
+    // pair-parallel one a single call picks for small shapes, more throughput)
     int r2 = gemm_split_pooled(q->r.algo, sl, p.m, p.n, p.k, p.alpha,
                                static_cast<const double *>(p.A), p.lda,
                                static_cast<const double *>(p.B), p.ldb, p.beta,
-                               static_cast<double *>(p.C), p.ldc, L.s);
+                               static_cast<double *>(p.C), p.ldc, L.s, false);
     if (r2 != MG_OK) q->res.status = r2;
   }
   (void)hipEventRecord(L.ev, L.s);
@@ -369,10 +371,10 @@ int server_submit(Server *S, const mg_request *r, uint64_t *ticket) {
   if (rc != MG_OK) return rc;
   int64_t bytes = es * (p.m * p.k + p.k * p.n + p.m * p.n);
   if (r->algo != MG_NATIVE) {
-    SplitLayout L;
-    rc = split_layout(r->algo, split_default_slices(r->algo), p.m, p.n, p.k, &L);
-    if (rc != MG_OK) return rc;
-    bytes += L.total;
+    const int64_t ws =
+        split_workspace_bytes(r->algo, split_default_slices(r->algo), p.m, p.n, p.k, false);
+    if (ws < 0) return MG_ERR_INVALID_ARG;
+    bytes += ws;
   }
   const int64_t t = now_ns();
   std::lock_guard<std::mutex> lk(S->mu);

@@ -33,7 +33,16 @@ int split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, const d
 
 // Work divisions of the product kernel; cfg < 0 picks by size.
 int split_num_cfgs();
-int split_pick_cfg(int algo, int64_t mp, int64_t np);
+// `latency`: one call on an otherwise idle device (the pair-parallel division
+// below two 128x128 tiles per CU); false: a device shared with other work
+// (fused divisions only, the most throughput per FLOP).  Both give the same
+// bits.
+int split_pick_cfg(int algo, int64_t mp, int64_t np, bool latency);
+// Workspace bytes the division `cfg` needs (<= the layout's total), and
+// those of the division split_pick_cfg would pick.
+int64_t split_ws_needed(const SplitLayout &L, int cfg);
+int64_t split_workspace_bytes(int algo, int slices, int64_t m, int64_t n, int64_t k,
+                              bool latency);
 
 // Slice products + recombination + epilogue from a prepared workspace.
 int split_multiply(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
@@ -44,9 +53,10 @@ int gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double alp
                const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
                double *C, int64_t ldc, void *ws, int64_t ws_bytes, hipStream_t s, int cfg = -1);
 
-// The same with a workspace from HIP's stream-ordered allocator on `s`.
+// The same with a workspace from HIP's stream-ordered allocator on `s`, of
+// the size the picked division needs (see split_pick_cfg for `latency`).
 int gemm_split_pooled(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
                       const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
-                      double *C, int64_t ldc, hipStream_t s);
+                      double *C, int64_t ldc, hipStream_t s, bool latency = true);
 
 }  // namespace mg

@@ -639,7 +639,7 @@ split_gemm_dma_kernel(SplitArgs a, int tiles_m, int tiles_n) {
 }
 
 // ---------------------------------------------------------------------------
-// Pair-parallel division (for grids with fewer than two 128x128 tiles per
+// Pair-parallel division (for grids with fewer than one 128x128 tile per
 // CU).  The s(s+1)/2 slice pairs, in the order the fused kernels walk them
 // (d = 2..s+1, then p), are cut into G contiguous groups of near-equal
 // size; workgroup (group g, tile) sums only its group's pairs and writes, for
@@ -958,9 +958,9 @@ int64_t seg_stages_of(int algo, int slices) {
   return st;
 }
 
-// Tiles of 128x128 below which the pair-parallel division is the default
-// (two per CU on the 256 CUs of MI355X), and the workgroups it aims for.
-constexpr int64_t kPairTilesBelow = 512;
+// Tiles of 128x128 below which the pair-parallel division serves (one per
+// CU on the 256 CUs of MI355X), and the workgroups it aims for.
+constexpr int64_t kPairTilesBelow = 256;
 constexpr int64_t kPairTargetWgs = 512;
 
 bool pairs_eligible(int64_t mp, int64_t np) { return (mp / 128) * (np / 128) < kPairTilesBelow; }
@@ -1089,18 +1089,22 @@ int split_num_cfgs() { return 16; }
 // Product-kernel work division (measured on MI355X at n = 4096): the 256x256
 // direct-to-LDS tile once every CU gets one, then the 128x256 one, else the
 // register-staged 128x128 tile.
-int split_pick_cfg(int algo, int64_t mp, int64_t np) {
-  // Below two 128x128 tiles per CU the pair-parallel division (15): the
-  // fused divisions would give too few workgroups, each walking all the
-  // slice pairs as one chain of dependent loads.
-  if (pairs_eligible(mp, np)) return 15;
+int split_pick_cfg(int algo, int64_t mp, int64_t np, bool latency) {
+  // Below one 128x128 tile per CU, for one call's latency, the pair-parallel
+  // division (15): the fused divisions would give too few workgroups, each
+  // walking all the slice pairs as one chain of dependent loads.  When the
+  // device is shared (the server's batches) the fused divisions give more
+  // throughput: same MFMA work without the partial sums' traffic.
+  if (latency && pairs_eligible(mp, np)) return 15;
   // INT8: the 16-wave 256x256 tile once it fills the chip.  BF16 keeps its
   // FP32 chunk accumulators in registers: 128x128 tiles on 8 waves, two
-  // workgroups per CU.
+  // workgroups per CU.  Below those, the 128x128 ring on 8 waves (whole
+  // INT8 call, n = 512 / 1024 / 2048: 130 / 229 / 402 us against 190 / 342
+  // / 573 for the register-staged 128x128 tile).
   if (algo == MG_SPLIT_I8 && (mp / 256) * (np / 256) >= 256) return 4;
-  if (algo == MG_SPLIT_BF16 && (mp / 128) * (np / 128) >= 512) return 12;
+  if (algo == MG_SPLIT_BF16) return 12;
   if ((mp / 128) * (np / 256) >= 256) return 2;
-  return 0;
+  return 14;
 }
 
 int split_multiply(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
@@ -1140,7 +1144,7 @@ int split_multiply(int algo, int slices, int64_t m, int64_t n, int64_t k, double
   a.seg_stages = (int)std::min<int64_t>(seg_stages, a.total_stages);
   a.alpha = alpha;
   a.beta = beta;
-  if (cfg < 0) cfg = split_pick_cfg(algo, L.mp, L.np);
+  if (cfg < 0) cfg = split_pick_cfg(algo, L.mp, L.np, true);
   switch (cfg) {
     case 0: return launch_split<2, 2, 4, 4>(algo, a, L, s);          // 128x128, 4 waves, registers
     case 1: return launch_split_dma<2, 2, 4, 4, 4>(algo, a, L, s);   // 128x128, 4 waves, ring of 4
@@ -1182,8 +1186,9 @@ int gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double alp
   if (rc != MG_OK) return rc;
   if (alpha == 0.0 || k == 0)  // C <- beta*C: A and B are not read
     return gemm_native(MG_F64, 0, m, n, 0, 0.0, nullptr, 1, nullptr, 1, beta, C, ldc, s);
-  if (ws == nullptr || ws_bytes < L.total) {
-    set_error("split workspace too small: need %lld bytes", (long long)L.total);
+  const int use = cfg < 0 ? split_pick_cfg(algo, L.mp, L.np, true) : cfg;
+  if (ws == nullptr || ws_bytes < split_ws_needed(L, use)) {
+    set_error("split workspace too small: need %lld bytes", (long long)split_ws_needed(L, use));
     return MG_ERR_INVALID_ARG;
   }
   rc = split_prepare(algo, slices, m, n, k, A, lda, B, ldb, ws, s);
@@ -1191,22 +1196,35 @@ int gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double alp
   return split_multiply(algo, slices, m, n, k, alpha, beta, C, ldc, ws, s, cfg);
 }
 
+int64_t split_ws_needed(const SplitLayout &L, int cfg) {
+  return cfg == 15 ? L.total : round_up(L.p_off + 8 * L.mp * L.np, 256);
+}
+
+int64_t split_workspace_bytes(int algo, int slices, int64_t m, int64_t n, int64_t k,
+                              bool latency) {
+  SplitLayout L;
+  if (split_layout(algo, slices, m, n, k, &L) != MG_OK) return -1;
+  return split_ws_needed(L, split_pick_cfg(algo, L.mp, L.np, latency));
+}
+
 int gemm_split_pooled(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
                       const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
-                      double *C, int64_t ldc, hipStream_t s) {
+                      double *C, int64_t ldc, hipStream_t s, bool latency) {
   if (m == 0 || n == 0) return MG_OK;
   SplitLayout L;
   int rc = split_layout(algo, slices, m, n, k, &L);
   if (rc != MG_OK) return rc;
   if (alpha == 0.0 || k == 0)
     return gemm_split(algo, slices, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, 0, s);
+  const int cfg = split_pick_cfg(algo, L.mp, L.np, latency);
+  const int64_t bytes = split_ws_needed(L, cfg);
   void *ws = nullptr;
-  hipError_t e = hipMallocAsync(&ws, (size_t)L.total, s);
+  hipError_t e = hipMallocAsync(&ws, (size_t)bytes, s);
   if (e != hipSuccess) {
-    set_error("hipMallocAsync(%lld bytes) failed: %s", (long long)L.total, hipGetErrorString(e));
+    set_error("hipMallocAsync(%lld bytes) failed: %s", (long long)bytes, hipGetErrorString(e));
     return MG_ERR_NO_MEMORY;
   }
-  rc = gemm_split(algo, slices, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ws, L.total, s);
+  rc = gemm_split(algo, slices, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ws, bytes, s, cfg);
   MG_HIP_TRY(hipFreeAsync(ws, s));
   return rc;
 }

@@ -1104,7 +1104,10 @@ int split_pick_cfg(int algo, int64_t mp, int64_t np, bool latency) {
   if (algo == MG_SPLIT_I8 && (mp / 256) * (np / 256) >= 256) return 4;
   if (algo == MG_SPLIT_BF16) return 12;
   if ((mp / 128) * (np / 256) >= 256) return 2;
-  return 14;
+  // 3-stage ring below one 128x128 tile per CU, 2-stage (two workgroups per
+  // CU) from there: alone / four streams at once, n = 1024: 228 / 72 us per
+  // call (3 stages) against 226 / 85; n = 2048: 424 / 399 against 406 / 350
+  return (mp / 128) * (np / 128) >= 256 ? 12 : 14;
 }
 
 int split_multiply(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,

@@ -303,14 +303,25 @@ int mg_plan_get_stats(const mg_plan *plan, mg_plan_stats *out);
 /* Frees the plan.  The caller must make sure no launch of it is pending. */
 int mg_plan_destroy(mg_plan *plan);
 
-/* One-shot: plan (heuristic table) + launch on `stream`.  algo must be
- * MG_NATIVE.  The plan of each distinct problem set is kept (the last 8 sets
+/* One-shot: plan (heuristic table) + launch on `stream`.
+ * MG_NATIVE: the plan of each distinct problem set is kept (the last 8 sets
  * per process, matched on device, dtype and every descriptor byte for byte)
  * with its launch captured in a HIP graph: a call whose problem set repeats
  * replays that graph instead of building and uploading a new work list (the
  * list holds pointers, extents and scalars only, so each replay reads the
  * operands' current contents).  An evicted plan's device memory is released
- * by a later library call once its last launch has completed. */
+ * by a later library call once its last launch has completed.
+ * MG_SPLIT_I8 / MG_SPLIT_BF16 (dtype MG_F64; MG_ERR_UNSUPPORTED otherwise):
+ * the split-precision method of mg_gemm on every problem, with the default
+ * slice count, in four launches for the whole batch -- exponents and slices
+ * of all problems (three preparation grids), then one grid of 128x128 output
+ * tiles over all problems, longest k first (Section 3.3: independent grids
+ * of one device run concurrently; here they share one launch).  The
+ * per-problem workspaces (the layout of mg_split_layout_query, one
+ * stream-ordered allocation freed on `stream` after the batch) and the
+ * descriptors are built per call; nothing is kept.  Each result equals
+ * mg_gemm(MG_F64, algo, ...) on that problem alone, bit for bit.
+ * MG_ERR_NO_MEMORY if the workspaces cannot be allocated. */
 int mg_gemm_batched(int dtype, int algo, int64_t count, const mg_problem *probs, void *stream);
 /* Calls of mg_gemm_batched so far that replayed a kept plan (hits) and that
  * built a new one (misses).  Either pointer may be NULL. */
@@ -338,8 +349,8 @@ int mg_gemm_batched_noalloc(int dtype, int64_t count, const mg_problem *probs, v
  * but-unfinished requests stay within `max_slots` and their bytes (A + B + C,
  * plus the split workspace for split requests) within `hbm_budget_bytes`, and
  * launches everything admitted so far as one batch on the next free stream
- * (one persistent grouped launch for the native requests, the split kernels
- * for split requests).  Batches on different streams run concurrently on the
+ * (one persistent grouped launch for the native requests, one batched split
+ * launch set per split algorithm, as in mg_gemm_batched).  Batches on different streams run concurrently on the
  * device (the paper's scheduler may run grids from several streams in
  * parallel, Section 3.3); requests that arrive while batches run are admitted
  * as slots and bytes free up and go out with the next batch.  A request's

@@ -387,11 +387,12 @@ def gemm_batched_noalloc(probs, dtype: int = F64, stream=None):
     check(lib().mg_gemm_batched_noalloc(dtype, n, arr, _stream_handle(stream)))
 
 
-def gemm_batched(probs, dtype: int = F64, stream=None):
-    """One-shot batched launch (mg_gemm_batched; a repeated problem set
-    replays its kept graph)."""
+def gemm_batched(probs, dtype: int = F64, stream=None, algo: int = NATIVE):
+    """One-shot batched launch (mg_gemm_batched).  NATIVE: a repeated problem
+    set replays its kept graph; SPLIT_I8 / SPLIT_BF16 (FP64 only): batched
+    split-precision launches, each result the single call's bits."""
     arr, n = _problems(probs)
-    check(lib().mg_gemm_batched(dtype, NATIVE, n, arr, _stream_handle(stream)))
+    check(lib().mg_gemm_batched(dtype, algo, n, arr, _stream_handle(stream)))
 
 
 def gemm_batched_cache_stats() -> dict:

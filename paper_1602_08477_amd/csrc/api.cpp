@@ -562,8 +562,12 @@ int mg_gemm_batched_noalloc(int dtype, int64_t count, const mg_problem *probs, v
 
 int mg_gemm_batched(int dtype, int algo, int64_t count, const mg_problem *probs, void *stream) {
   clear_error();
-  if (algo != MG_NATIVE) {
-    set_error("batched GEMM supports MG_NATIVE only");
+  if (algo != MG_NATIVE && algo != MG_SPLIT_I8 && algo != MG_SPLIT_BF16) {
+    set_error("unknown algo %d", algo);
+    return MG_ERR_INVALID_ARG;
+  }
+  if (algo != MG_NATIVE && dtype != MG_F64) {
+    set_error("split algorithms take FP64 operands");
     return MG_ERR_UNSUPPORTED;
   }
   reap_deferred(false);
@@ -571,6 +575,8 @@ int mg_gemm_batched(int dtype, int algo, int64_t count, const mg_problem *probs,
   if (rc != MG_OK) return rc;
   if (count == 0) return MG_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (algo != MG_NATIVE)  // built per call (its workspace is per call too)
+    return gemm_split_batched(algo, split_default_slices(algo), count, probs, s);
   int dev = 0;
   MG_HIP_TRY(hipGetDevice(&dev));
   const uint64_t h = hash_problems(dtype, count, probs);

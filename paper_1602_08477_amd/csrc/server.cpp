@@ -183,17 +183,18 @@ void launch_batch(Server *S, Lane &L, int64_t batch_id) {
                                p.k, p.alpha, p.A, p.lda, p.B, p.ldb, p.beta, p.C, p.ldc, L.s);
     if (r2 != MG_OK) q->res.status = r2;
   }
-  for (Req *q : L.batch) {
-    if (q->r.algo == MG_NATIVE) continue;
-    const mg_problem &p = q->r.p;
-    const int sl = split_default_slices(q->r.algo);
-    // the batches share the device: the fused divisions (same bits as the
-    // pair-parallel one a single call picks for small shapes, more throughput)
-    int r2 = gemm_split_pooled(q->r.algo, sl, p.m, p.n, p.k, p.alpha,
-                               static_cast<const double *>(p.A), p.lda,
-                               static_cast<const double *>(p.B), p.ldb, p.beta,
-                               static_cast<double *>(p.C), p.ldc, L.s, false);
-    if (r2 != MG_OK) q->res.status = r2;
+  // Split requests: one batched split launch set per algorithm (each result
+  // the same bits as the request alone).
+  for (const int algo : {MG_SPLIT_I8, MG_SPLIT_BF16}) {
+    std::vector<mg_problem> ps;
+    for (Req *q : L.batch)
+      if (q->r.algo == algo) ps.push_back(q->r.p);
+    if (ps.empty()) continue;
+    const int r2 = gemm_split_batched(algo, split_default_slices(algo), (int64_t)ps.size(),
+                                      ps.data(), L.s);
+    if (r2 != MG_OK)
+      for (Req *q : L.batch)
+        if (q->r.algo == algo) q->res.status = r2;
   }
   (void)hipEventRecord(L.ev, L.s);
 }

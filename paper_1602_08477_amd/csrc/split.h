@@ -59,4 +59,11 @@ int gemm_split_pooled(int algo, int slices, int64_t m, int64_t n, int64_t k, dou
                       const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
                       double *C, int64_t ldc, hipStream_t s, bool latency = true);
 
+// Many independent FP64 problems (validated descriptors) in one set of
+// launches: per-problem workspaces in one stream-ordered allocation, batched
+// preparation, one product launch over the output tiles of all problems.
+// Each result equals a single call's bit for bit.
+int gemm_split_batched(int algo, int slices, int64_t count, const mg_problem *probs,
+                       hipStream_t s);
+
 }  // namespace mg

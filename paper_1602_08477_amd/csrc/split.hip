@@ -18,6 +18,11 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <utility>
+#include <vector>
 
 #include "gemm_native.h"
 
@@ -36,24 +41,38 @@ __device__ __forceinline__ int exp_of(double x) {
 }
 
 // ------------------------------------------------------------ step 1: scales
-__global__ void fill_int_kernel(int *p, int count, int v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// The preparation kernels are written as bodies over a block index so that
+// the single-problem launches and the batched launches (one grid over the
+// blocks of many problems) run the same code.  All use 256 threads.
+__device__ __forceinline__ void fill_int_body(int *p, int count, int v, int block) {
+  const int i = block * 256 + threadIdx.x;
   if (i < count) p[i] = v;
+}
+
+__global__ void fill_int_kernel(int *p, int count, int v) {
+  fill_int_body(p, count, v, blockIdx.x);
 }
 
 constexpr int kColRows = 64;  // rows of B per thread in col_exp_kernel
 
-__global__ void col_exp_kernel(const double *B, int64_t ldb, int k, int n, int *F) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// Column exponents of B for the 256 columns of block `bx`, over the k chunks
+// by, by + gy, ... (the maximum is order-independent).
+__device__ __forceinline__ void col_exp_body(const double *B, int64_t ldb, int k, int n, int *F,
+                                             int bx, int by, int gy) {
+  const int j = bx * 256 + threadIdx.x;
   if (j >= n) return;
   const int nchunks = (k + kColRows - 1) / kColRows;
-  for (int ch = blockIdx.y; ch < nchunks; ch += gridDim.y) {
+  for (int ch = by; ch < nchunks; ch += gy) {
     int e = INT_MIN;
     const int r1 = min(k, (ch + 1) * kColRows);
 #pragma unroll 8
     for (int r = ch * kColRows; r < r1; ++r) e = max(e, exp_of(B[(int64_t)r * ldb + j]));
     if (e != INT_MIN) atomicMax(F + j, e);
   }
+}
+
+__global__ void col_exp_kernel(const double *B, int64_t ldb, int k, int n, int *F) {
+  col_exp_body(B, ldb, k, n, F, blockIdx.x, blockIdx.y, gridDim.y);
 }
 
 // ------------------------------------------------------------ step 2: slices
@@ -105,11 +124,11 @@ __device__ __forceinline__ void slice_round(double *r, int *q, int bits) {
 // quads (4 consecutive k) tid, tid+256, ...; rows up to 4096 long stay in
 // registers between the two passes, longer rows are read again (from L2).
 template <int ESZ>
-__global__ __launch_bounds__(256) void slice_rows_exp_kernel(const double *A, int64_t lda, int m,
-                                                             int k, int mp, int64_t kp, int *E,
-                                                             int s, int bits, unsigned char *out) {
+__device__ __forceinline__ void slice_rows_exp_body(const double *A, int64_t lda, int m, int k,
+                                                    int mp, int64_t kp, int *E, int s, int bits,
+                                                    unsigned char *out, int i) {
   constexpr int QPT = 4;  // quads per thread held in registers
-  const int i = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   const bool live = i < m;
   const double *row = A + (int64_t)(live ? i : 0) * lda;
   const int64_t quads = kp / 4;
@@ -165,16 +184,23 @@ __global__ __launch_bounds__(256) void slice_rows_exp_kernel(const double *A, in
   }
 }
 
+template <int ESZ>
+__global__ __launch_bounds__(256) void slice_rows_exp_kernel(const double *A, int64_t lda, int m,
+                                                             int k, int mp, int64_t kp, int *E,
+                                                             int s, int bits, unsigned char *out) {
+  slice_rows_exp_body<ESZ>(A, lda, m, k, mp, kp, E, s, bits, out, blockIdx.x);
+}
+
 // B slices, stored transposed [s][np][kp] (k contiguous per column of B):
 // a 64 x 64 block of B is transposed through LDS.
 template <int ESZ>
-__global__ __launch_bounds__(256) void slice_cols_kernel(const double *B, int64_t ldb, int k, int n,
-                                                         int np, int64_t kp, int *F, int s,
-                                                         int bits, unsigned char *out) {
+__device__ __forceinline__ void slice_cols_body(const double *B, int64_t ldb, int k, int n,
+                                                int np, int64_t kp, int *F, int s, int bits,
+                                                unsigned char *out, int block) {
   __shared__ double T[64][65];
   const int64_t kblocks = kp / 64;
-  const int j0 = (int)(blockIdx.x / kblocks) * 64;
-  const int64_t k0 = (blockIdx.x % kblocks) * 64;
+  const int j0 = (int)(block / kblocks) * 64;
+  const int64_t k0 = (block % kblocks) * 64;
   const int tid = threadIdx.x;
   for (int e = tid; e < 64 * 64; e += 256) {
     const int kk = e >> 6, jj = e & 63;
@@ -204,6 +230,13 @@ __global__ __launch_bounds__(256) void slice_cols_kernel(const double *B, int64_
     for (int h = 0; h < 16 / CW; ++h)
       *reinterpret_cast<i4v *>(o + t * slice_bytes + h * 16) = SlicePack<ESZ>::pack(q + h * CW);
   }
+}
+
+template <int ESZ>
+__global__ __launch_bounds__(256) void slice_cols_kernel(const double *B, int64_t ldb, int k, int n,
+                                                         int np, int64_t kp, int *F, int s,
+                                                         int bits, unsigned char *out) {
+  slice_cols_body<ESZ>(B, ldb, k, n, np, kp, F, s, bits, out, blockIdx.x);
 }
 
 // ------------------------------------------------- steps 3-4: slice products
@@ -513,23 +546,19 @@ __device__ __forceinline__ void dma16(const unsigned char *src, unsigned char *l
                                    0);
 }
 
+// One output tile (m0, n0) of the product: every slice pair over every k
+// stage, the folds, the epilogue.  `plane0`: the tile's BM*BN partial sums.
 // `a.seg_stages` and `a.total_stages` count SB-byte stages here.
 template <int ALGO, int WGM, int WGN, int FMW, int FNW, int NS, int SB>
-__global__ __launch_bounds__((SplitDmaShape<WGM, WGN, FMW, FNW, NS, SB>::THREADS),
-                             (SplitDmaShape<WGM, WGN, FMW, FNW, NS, SB>::MINW)) void
-split_gemm_dma_kernel(SplitArgs a, int tiles_m, int tiles_n) {
+__device__ __forceinline__ void split_dma_tile(const SplitArgs &a, int m0, int n0, double *plane0,
+                                               unsigned char *lds) {
   typedef SplitMma<ALGO> M;
   typedef typename M::acc_t Acc;
   typedef SplitDmaShape<WGM, WGN, FMW, FNW, NS, SB> S;
   // FP32 chunk of 256 k for BF16 (512 bytes), in stages
   constexpr int CHUNK = M::CHUNK_STAGES > 0 ? 512 / SB : 0;
-  constexpr int BM = S::BM, BN = S::BN, STAGE = S::STAGE;
+  constexpr int BM = S::BM, STAGE = S::STAGE;
   constexpr int DPS = S::IA + S::IB;  // DMA instructions per step per wave
-  extern __shared__ __align__(16) unsigned char lds[];
-
-  int tm, tn;
-  grouped_tile(xcd_remap(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, tm, tn);
-  const int m0 = tm * BM, n0 = tn * S::BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave / WGN) * 16 * FMW, wn0 = (wave % WGN) * 16 * FNW;
   const int g = lane >> 4, l16 = lane & 15;
@@ -549,7 +578,7 @@ split_gemm_dma_kernel(SplitArgs a, int tiles_m, int tiles_n) {
     const int row = S::RPI * (wave * S::IB + u) + lane / S::CPR;
     bsrc[u] = (int64_t)(n0 + row) * a.kp_bytes + swz_chunk<SB>(row, lane % S::CPR) * 16;
   }
-  double *plane = a.P + (int64_t)blockIdx.x * (BM * BN) + tid;  // this lane's partial sums
+  double *plane = plane0 + tid;  // this lane's partial sums
 
   auto issue = [&](const Step &x, int stage) {
     const int64_t koff = (int64_t)(x.seg * a.seg_stages + x.st) * SB;
@@ -636,6 +665,18 @@ split_gemm_dma_kernel(SplitArgs a, int tiles_m, int tiles_n) {
   const bool only = a.s == 1 && a.seg_stages >= a.total_stages;  // a single fold in all
   finish_tile<M, FMW, FNW, S::THREADS>(a, acc, dacc, plane, only, m0 + wm0 + 4 * g,
                                        n0 + wn0 + l16);
+}
+
+template <int ALGO, int WGM, int WGN, int FMW, int FNW, int NS, int SB>
+__global__ __launch_bounds__((SplitDmaShape<WGM, WGN, FMW, FNW, NS, SB>::THREADS),
+                             (SplitDmaShape<WGM, WGN, FMW, FNW, NS, SB>::MINW)) void
+split_gemm_dma_kernel(SplitArgs a, int tiles_m, int tiles_n) {
+  typedef SplitDmaShape<WGM, WGN, FMW, FNW, NS, SB> S;
+  extern __shared__ __align__(16) unsigned char lds[];
+  int tm, tn;
+  grouped_tile(xcd_remap(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, tm, tn);
+  split_dma_tile<ALGO, WGM, WGN, FMW, FNW, NS, SB>(
+      a, tm * S::BM, tn * S::BN, a.P + (int64_t)blockIdx.x * (S::BM * S::BN), lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -937,6 +978,103 @@ int launch_split(int algo, const SplitArgs &a, const SplitLayout &L, hipStream_t
                                : launch_split_t<MG_SPLIT_I8, WGM, WGN, FMW, FNW>(a, L, s);
 }
 
+// ---------------------------------------------------------------------------
+// Batched split GEMM: many independent problems in one set of launches.
+// Every problem keeps the single-problem workspace layout, all of them in one
+// allocation.  The preparation launches run one grid over the blocks of all
+// problems (a workgroup finds its problem by binary search over the block
+// prefix sums); the product launch runs one workgroup per output tile of
+// every problem, longest k first, with the tile code of the fused 128x128
+// division -- so each result is the one a single call gives, bit for bit.
+// Only tiles that hold outputs are run, and only the rows of A / columns of
+// B those tiles read are sliced.
+struct SplitPrepDesc {
+  const double *A, *B;
+  int64_t lda, ldb, kp;
+  int m, n, k, mp, np;
+  int nr;      // columns of B the product tiles read: n rounded up to 128
+  int cx, cy;  // column-exponent blocks: cx blocks of 256 columns x cy k-chunk strides
+  int *E, *F;
+  unsigned char *As, *Bs;
+};
+
+struct SplitTileRec {
+  int prob, m0, n0, local;  // local: the tile's index in its problem's partial-sum region
+};
+
+// 128x128 tile on 8 wavefronts, 2-stage ring of 128 bytes (division 12).
+typedef SplitDmaShape<2, 4, 4, 2, 2, 128> BatchShape;
+
+// Problem that owns block b of a batched launch: the last i with first[i] <= b.
+__device__ __forceinline__ int batch_problem(const int *first, int count, int b) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void batched_fill_kernel(const SplitPrepDesc *d,
+                                                           const int *first, int count) {
+  const int i = batch_problem(first, count, blockIdx.x);
+  fill_int_body(d[i].F, d[i].nr, INT_MIN, blockIdx.x - first[i]);
+}
+
+// Blocks [0, cx*cy) of a problem find column exponents of B; each further
+// block finds the exponent of one row of A and slices it.
+template <int ESZ>
+__global__ __launch_bounds__(256) void batched_exp_rows_kernel(const SplitPrepDesc *d,
+                                                               const int *first, int count,
+                                                               int s, int bits) {
+  const int i = batch_problem(first, count, blockIdx.x);
+  const SplitPrepDesc &q = d[i];
+  const int lb = blockIdx.x - first[i], ncol = q.cx * q.cy;
+  if (lb < ncol) col_exp_body(q.B, q.ldb, q.k, q.n, q.F, lb % q.cx, lb / q.cx, q.cy);
+  else slice_rows_exp_body<ESZ>(q.A, q.lda, q.m, q.k, q.mp, q.kp, q.E, s, bits, q.As, lb - ncol);
+}
+
+template <int ESZ>
+__global__ __launch_bounds__(256) void batched_slice_cols_kernel(const SplitPrepDesc *d,
+                                                                 const int *first, int count,
+                                                                 int s, int bits) {
+  const int i = batch_problem(first, count, blockIdx.x);
+  const SplitPrepDesc &q = d[i];
+  slice_cols_body<ESZ>(q.B, q.ldb, q.k, q.n, q.np, q.kp, q.F, s, bits, q.Bs,
+                       blockIdx.x - first[i]);
+}
+
+template <int ALGO>
+__global__ __launch_bounds__(BatchShape::THREADS, BatchShape::MINW) void split_batched_kernel(
+    const SplitArgs *args, const SplitTileRec *recs) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const SplitTileRec r = recs[blockIdx.x];
+  const SplitArgs a = args[r.prob];
+  split_dma_tile<ALGO, 2, 4, 4, 2, 2, 128>(
+      a, r.m0, r.n0, a.P + (int64_t)r.local * (BatchShape::BM * BatchShape::BN), lds);
+}
+
+template <int ALGO>
+int launch_batched_t(const SplitArgs *d_args, const SplitPrepDesc *d_desc, const int *d_first,
+                     int nl, const int64_t *blocks, const SplitTileRec *d_recs, int ntiles,
+                     int slices, hipStream_t s) {
+  constexpr int ESZ = ALGO == MG_SPLIT_BF16 ? 2 : 1;
+  const int bits = split_bits(ALGO);
+  static int once = ensure_lds(split_batched_kernel<ALGO>, BatchShape::LDS_BYTES);
+  if (once != MG_OK) return once;
+  hipLaunchKernelGGL(batched_fill_kernel, dim3((unsigned)blocks[0]), dim3(256), 0, s, d_desc,
+                     d_first, nl);
+  hipLaunchKernelGGL(batched_exp_rows_kernel<ESZ>, dim3((unsigned)blocks[1]), dim3(256), 0, s,
+                     d_desc, d_first + (nl + 1), nl, slices, bits);
+  hipLaunchKernelGGL(batched_slice_cols_kernel<ESZ>, dim3((unsigned)blocks[2]), dim3(256), 0, s,
+                     d_desc, d_first + 2 * (nl + 1), nl, slices, bits);
+  hipLaunchKernelGGL(split_batched_kernel<ALGO>, dim3((unsigned)ntiles),
+                     dim3(BatchShape::THREADS), BatchShape::LDS_BYTES, s, d_args, d_recs);
+  MG_HIP_TRY(hipGetLastError());
+  return MG_OK;
+}
+
 }  // namespace
 
 int split_default_slices(int algo) { return algo == MG_SPLIT_BF16 ? 6 : 7; }
@@ -1229,6 +1367,217 @@ int gemm_split_pooled(int algo, int slices, int64_t m, int64_t n, int64_t k, dou
   }
   rc = gemm_split(algo, slices, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ws, bytes, s, cfg);
   MG_HIP_TRY(hipFreeAsync(ws, s));
+  return rc;
+}
+
+namespace {
+
+// Host copies of batched-launch descriptors, each released once its stream
+// has passed the copy that reads it.
+std::mutex g_hold_mu;
+std::vector<std::pair<std::vector<unsigned char> *, hipEvent_t>> g_hold;
+
+void reap_holds() {
+  std::lock_guard<std::mutex> lk(g_hold_mu);
+  std::vector<std::pair<std::vector<unsigned char> *, hipEvent_t>> keep;
+  for (auto &h : g_hold) {
+    if (hipEventQuery(h.second) == hipSuccess) {
+      delete h.first;
+      (void)hipEventDestroy(h.second);
+    } else {
+      keep.push_back(h);
+    }
+  }
+  g_hold.swap(keep);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+int gemm_split_batched(int algo, int slices, int64_t count, const mg_problem *probs,
+                       hipStream_t s) {
+  if (algo != MG_SPLIT_I8 && algo != MG_SPLIT_BF16) {
+    set_error("not a split algorithm: %d", algo);
+    return MG_ERR_INVALID_ARG;
+  }
+  reap_holds();
+  const int64_t seg = seg_stages_of(algo, slices);
+  if (seg < 1) {
+    set_error("too many slices for exact INT32 accumulation");
+    return MG_ERR_INVALID_ARG;
+  }
+  typedef BatchShape S;
+  // Degenerate problems as a single call runs them; the rest are batched.
+  std::vector<int64_t> live;
+  for (int64_t i = 0; i < count; ++i) {
+    const mg_problem &q = probs[i];
+    if (q.m == 0 || q.n == 0) continue;
+    if (q.alpha == 0.0 || q.k == 0) {  // C <- beta*C: A and B are not read
+      const int rc = gemm_native(MG_F64, 0, q.m, q.n, 0, 0.0, nullptr, 1, nullptr, 1, q.beta,
+                                 q.C, q.ldc, s);
+      if (rc != MG_OK) return rc;
+      continue;
+    }
+    live.push_back(i);
+  }
+  const int nl = (int)live.size();
+  if (nl == 0) return MG_OK;
+  if (live.size() > (size_t)(INT32_MAX / 4)) {
+    set_error("too many problems in one batch");
+    return MG_ERR_INVALID_ARG;
+  }
+  std::vector<SplitLayout> L((size_t)nl);
+  std::vector<int64_t> woff((size_t)nl);
+  int64_t wbytes = 0;
+  for (int j = 0; j < nl; ++j) {
+    const mg_problem &q = probs[live[(size_t)j]];
+    int rc = split_layout(algo, slices, q.m, q.n, q.k, &L[(size_t)j]);
+    if (rc != MG_OK) return rc;
+    woff[(size_t)j] = wbytes;
+    wbytes += split_ws_needed(L[(size_t)j], 12);  // the fused divisions' workspace
+  }
+  // Longest k first: the costliest tiles start first and the short ones
+  // fill in behind them.
+  std::vector<int> ord((size_t)nl);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(),
+                   [&](int x, int y) { return L[(size_t)x].kp > L[(size_t)y].kp; });
+
+  // Descriptor block: args [nl], prep descriptors [nl], three block prefix
+  // arrays [nl + 1], tile records.
+  std::vector<SplitArgs> args((size_t)nl);
+  std::vector<SplitPrepDesc> desc((size_t)nl);
+  std::vector<int> first((size_t)3 * (nl + 1), 0);
+  std::vector<SplitTileRec> recs;
+  int64_t blocks[3] = {0, 0, 0};
+  for (int j = 0; j < nl; ++j) {
+    const mg_problem &q = probs[live[(size_t)j]];
+    const SplitLayout &l = L[(size_t)j];
+    const int64_t mr = round_up(q.m, (int64_t)S::BM), nr = round_up(q.n, (int64_t)S::BN);
+    const int64_t nchunks = ceil_div(q.k, kColRows);
+    const int64_t cx = ceil_div(q.n, 256), cy = std::min<int64_t>(nchunks, 256);
+    const int64_t nb[3] = {ceil_div(nr, 256), cx * cy + mr, (nr / 64) * (l.kp / 64)};
+    for (int w = 0; w < 3; ++w) {
+      first[(size_t)w * (nl + 1) + j] = (int)blocks[w];
+      blocks[w] += nb[w];
+      if (blocks[w] * 256 > (int64_t)UINT32_MAX) {
+        set_error("split batch too large for one dispatch");
+        return MG_ERR_INVALID_ARG;
+      }
+    }
+  }
+  for (int w = 0; w < 3; ++w) first[(size_t)w * (nl + 1) + nl] = (int)blocks[w];
+  for (int j : ord) {
+    const mg_problem &q = probs[live[(size_t)j]];
+    const SplitLayout &l = L[(size_t)j];
+    const int64_t tm = ceil_div(q.m, (int64_t)S::BM), tn = ceil_div(q.n, (int64_t)S::BN);
+    const int64_t tn_all = l.np / S::BN;
+    for (int64_t a = 0; a < tm; ++a)
+      for (int64_t b = 0; b < tn; ++b)
+        recs.push_back(SplitTileRec{j, (int)(a * S::BM), (int)(b * S::BN), (int)(a * tn_all + b)});
+  }
+  if (recs.size() * S::THREADS > (size_t)UINT32_MAX) {
+    set_error("split batch too large for one dispatch");
+    return MG_ERR_INVALID_ARG;
+  }
+  const size_t o_args = 0;
+  const size_t o_desc = align256(o_args + args.size() * sizeof(SplitArgs));
+  const size_t o_first = align256(o_desc + desc.size() * sizeof(SplitPrepDesc));
+  const size_t o_recs = align256(o_first + first.size() * sizeof(int));
+  const size_t meta = align256(o_recs + recs.size() * sizeof(SplitTileRec));
+
+  void *dev = nullptr;
+  hipError_t e = hipMallocAsync(&dev, (size_t)wbytes + meta, s);
+  if (e != hipSuccess) {
+    set_error("hipMallocAsync(%lld bytes) failed: %s", (long long)(wbytes + (int64_t)meta),
+              hipGetErrorString(e));
+    return MG_ERR_NO_MEMORY;
+  }
+  unsigned char *w = static_cast<unsigned char *>(dev);
+  const int bits = split_bits(algo);
+  for (int j = 0; j < nl; ++j) {
+    const mg_problem &q = probs[live[(size_t)j]];
+    const SplitLayout &l = L[(size_t)j];
+    unsigned char *base = w + woff[(size_t)j];
+    SplitArgs &a = args[(size_t)j];
+    a.P = reinterpret_cast<double *>(base + l.p_off);
+    a.Q = nullptr;
+    a.As = base + l.a_off;
+    a.Bs = base + l.b_off;
+    a.E = reinterpret_cast<const int *>(base + l.e_off);
+    a.F = reinterpret_cast<const int *>(base + l.f_off);
+    a.C = static_cast<double *>(q.C);
+    a.ldc = q.ldc;
+    a.m = (int)q.m;
+    a.n = (int)q.n;
+    a.mp = (int)l.mp;
+    a.np = (int)l.np;
+    a.kp_bytes = l.kp * l.elem_bytes;
+    a.s = slices;
+    a.bits = bits;
+    a.total_stages = (int)(a.kp_bytes / kStageBytes);
+    a.seg_stages = (int)std::min<int64_t>(seg, a.total_stages);
+    a.alpha = q.alpha;
+    a.beta = q.beta;
+    SplitPrepDesc &d = desc[(size_t)j];
+    d.A = static_cast<const double *>(q.A);
+    d.B = static_cast<const double *>(q.B);
+    d.lda = q.lda;
+    d.ldb = q.ldb;
+    d.kp = l.kp;
+    d.m = (int)q.m;
+    d.n = (int)q.n;
+    d.k = (int)q.k;
+    d.mp = (int)l.mp;
+    d.np = (int)l.np;
+    d.nr = (int)round_up(q.n, (int64_t)S::BN);
+    d.cx = (int)ceil_div(q.n, 256);
+    d.cy = (int)std::min<int64_t>(ceil_div(q.k, kColRows), 256);
+    d.E = reinterpret_cast<int *>(base + l.e_off);
+    d.F = reinterpret_cast<int *>(base + l.f_off);
+    d.As = base + l.a_off;
+    d.Bs = base + l.b_off;
+  }
+  auto *host = new std::vector<unsigned char>(meta, 0);
+  unsigned char *h = host->data();
+  std::memcpy(h + o_args, args.data(), args.size() * sizeof(SplitArgs));
+  std::memcpy(h + o_desc, desc.data(), desc.size() * sizeof(SplitPrepDesc));
+  std::memcpy(h + o_first, first.data(), first.size() * sizeof(int));
+  std::memcpy(h + o_recs, recs.data(), recs.size() * sizeof(SplitTileRec));
+  unsigned char *dm = w + wbytes;
+  int rc = MG_OK;
+  e = hipMemcpyAsync(dm, h, meta, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) {
+    set_error("hipMemcpyAsync failed: %s", hipGetErrorString(e));
+    rc = MG_ERR_HIP;
+  }
+  if (rc == MG_OK) {
+    const auto *d_args = reinterpret_cast<const SplitArgs *>(dm + o_args);
+    const auto *d_desc = reinterpret_cast<const SplitPrepDesc *>(dm + o_desc);
+    const auto *d_first = reinterpret_cast<const int *>(dm + o_first);
+    const auto *d_recs = reinterpret_cast<const SplitTileRec *>(dm + o_recs);
+    rc = algo == MG_SPLIT_BF16
+             ? launch_batched_t<MG_SPLIT_BF16>(d_args, d_desc, d_first, nl, blocks, d_recs,
+                                               (int)recs.size(), slices, s)
+             : launch_batched_t<MG_SPLIT_I8>(d_args, d_desc, d_first, nl, blocks, d_recs,
+                                             (int)recs.size(), slices, s);
+  }
+  hipEvent_t ev = nullptr;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess &&
+      hipEventRecord(ev, s) == hipSuccess) {
+    std::lock_guard<std::mutex> lk(g_hold_mu);
+    g_hold.emplace_back(host, ev);
+  } else {  // cannot tell when the copy is done: wait for it
+    (void)hipStreamSynchronize(s);
+    if (ev) (void)hipEventDestroy(ev);
+    delete host;
+  }
+  e = hipFreeAsync(dev, s);
+  if (rc == MG_OK && e != hipSuccess) {
+    set_error("hipFreeAsync failed: %s", hipGetErrorString(e));
+    rc = MG_ERR_HIP;
+  }
   return rc;
 }
 

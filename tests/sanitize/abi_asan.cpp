@@ -121,6 +121,10 @@ int main() {
   EXPECT(mg_gemm_batched(MG_F64, MG_NATIVE, 5, probs.data(), nullptr) == MG_ERR_INVALID_ARG);
   EXPECT(mg_gemm_batched(MG_F64, MG_NATIVE, -1, probs.data(), nullptr) == MG_ERR_INVALID_ARG);
   EXPECT(mg_gemm_batched(MG_F64, MG_NATIVE, 0, nullptr, nullptr) == MG_OK);
+  EXPECT(mg_gemm_batched(MG_F32, MG_SPLIT_I8, 5, probs.data(), nullptr) == MG_ERR_UNSUPPORTED);
+  EXPECT(mg_gemm_batched(MG_F64, 9, 5, probs.data(), nullptr) == MG_ERR_INVALID_ARG);
+  EXPECT(mg_gemm_batched(MG_F64, MG_SPLIT_BF16, 5, probs.data(), nullptr) == MG_ERR_INVALID_ARG);
+  EXPECT(mg_gemm_batched(MG_F64, MG_SPLIT_I8, 0, nullptr, nullptr) == MG_OK);
   EXPECT(mg_gemm_batched_noalloc(MG_F64, 0, nullptr, nullptr) == MG_OK);
   // server request validation (host simulation: nothing touches a device)
   mg_server_opts o{};

@@ -94,6 +94,30 @@ def test_invalid_arguments(kw, code):
     assert mg.last_error() != ""
 
 
+def _fake_batch(count):
+    P = mg.Problem * count
+    return P(*[mg.Problem(8, 8, 8, 1.0, 1.0, 0x10000000 + 0x1000 * (3 * i), 8,
+                          0x10000000 + 0x1000 * (3 * i + 1), 8,
+                          0x10000000 + 0x1000 * (3 * i + 2), 8) for i in range(count)])
+
+
+def test_batched_algorithm_checks_without_gpu():
+    """mg_gemm_batched: split algorithms take FP64 only, unknown algorithms
+    and bad descriptors are rejected before anything touches a device."""
+    arr = _fake_batch(3)
+    assert mg.lib().mg_gemm_batched(mg.F32, mg.SPLIT_I8, 3, arr, NULL) == mg.ERR_UNSUPPORTED
+    assert mg.lib().mg_gemm_batched(mg.F32, mg.SPLIT_BF16, 3, arr, NULL) == mg.ERR_UNSUPPORTED
+    assert mg.lib().mg_gemm_batched(mg.F64, 9, 3, arr, NULL) == mg.ERR_INVALID_ARG
+    arr[1].lda = 2
+    for algo in (mg.SPLIT_I8, mg.SPLIT_BF16):
+        assert mg.lib().mg_gemm_batched(mg.F64, algo, 3, arr, NULL) == mg.ERR_INVALID_ARG
+        assert "problem 1" in mg.last_error()
+    arr[1].lda = 8
+    arr[2].C = arr[0].C  # outputs overlap
+    assert mg.lib().mg_gemm_batched(mg.F64, mg.SPLIT_I8, 3, arr, NULL) == mg.ERR_INVALID_ARG
+    assert mg.lib().mg_gemm_batched(mg.F64, mg.SPLIT_I8, 0, None, NULL) == mg.OK
+
+
 def test_empty_problem_is_ok_without_gpu():
     assert call_gemm(m=0) == mg.OK
     assert call_gemm(n=0, C=NULL) == mg.OK

@@ -99,7 +99,9 @@ def test_continuous_batching_groups_late_arrivals():
     ops = FakeOperands()
     with mg.Server(n_streams=1, max_batch=64, simulate=True, sim_tflops=1.0,
                    sim_launch_ns=0) as srv:
-        first = srv.submit_request(ops.request(1024))  # ~2 ms modeled
+        # ~17 ms modeled: the late requests all arrive while it runs, even on
+        # a loaded host
+        first = srv.submit_request(ops.request(2048))
         time.sleep(0.0005)
         late = [srv.submit_request(ops.request(64)) for _ in range(10)]
         r0 = srv.wait(first)

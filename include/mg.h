@@ -74,8 +74,9 @@ int mg_version(void);
  * elements per thread in the paper's terms, Table 2 and Section 3.4) is
  * chosen by the library from the shape.  The split algorithms use the
  * default slice count (mg_split_default_slices) and take their workspace
- * from HIP's stream-ordered allocator on `stream` (released on the same
- * stream); use mg_gemm_split to supply the workspace instead. */
+ * from the library's stream-ordered workspace pool on `stream` (released on
+ * the same stream; see mg_release_cached_memory); use mg_gemm_split to
+ * supply the workspace instead. */
 int mg_gemm(int dtype, int algo, int64_t m, int64_t n, int64_t k, double alpha,
             const void *A, int64_t lda, const void *B, int64_t ldb, double beta,
             void *C, int64_t ldc, void *stream);
@@ -205,6 +206,13 @@ int mg_gemm_split_cfg(int algo, int slices, int cfg, int64_t m, int64_t n, int64
                       double beta, double *C, int64_t ldc, void *workspace,
                       int64_t workspace_bytes, void *stream);
 
+/* Split workspaces come from a stream-ordered pool the library creates per
+ * device (the caller's default pool is not touched).  The pool keeps freed
+ * blocks for reuse, so repeated calls do not go back to the device
+ * allocator; this trims every such pool, returning the blocks no pending
+ * work uses.  MG_OK, or MG_ERR_HIP. */
+int mg_release_cached_memory(void);
+
 /* ------------------------------------------------------- batched GEMM --
  * Many independent problems C_i <- alpha_i A_i B_i + beta_i C_i (each the
  * Section 4.2 operation) in ONE persistent launch.  A plan validates the
@@ -314,11 +322,12 @@ int mg_plan_destroy(mg_plan *plan);
  * MG_SPLIT_I8 / MG_SPLIT_BF16 (dtype MG_F64; MG_ERR_UNSUPPORTED otherwise):
  * the split-precision method of mg_gemm on every problem, with the default
  * slice count, in four launches for the whole batch -- exponents and slices
- * of all problems (three preparation grids), then one grid of 128x128 output
- * tiles over all problems, longest k first (Section 3.3: independent grids
- * of one device run concurrently; here they share one launch).  The
- * per-problem workspaces (the layout of mg_split_layout_query, one
- * stream-ordered allocation freed on `stream` after the batch) and the
+ * of all problems (three preparation grids), then one grid of 64x64 output
+ * tiles over all problems, longest k first, with the FP64 partial sums in
+ * registers (Section 3.3: independent grids of one device run concurrently;
+ * here they share one launch).  The per-problem workspaces (exponents and
+ * slices padded to 64 rows / columns and 128 k, in one allocation from the
+ * library's workspace pool, freed on `stream` after the batch) and the
  * descriptors are built per call; nothing is kept.  Each result equals
  * mg_gemm(MG_F64, algo, ...) on that problem alone, bit for bit.
  * MG_ERR_NO_MEMORY if the workspaces cannot be allocated. */

@@ -238,6 +238,11 @@ def split_num_cfgs() -> int:
     return lib().mg_split_num_cfgs()
 
 
+def release_cached_memory() -> None:
+    """Trim the library's split-workspace pools (mg_release_cached_memory)."""
+    check(lib().mg_release_cached_memory())
+
+
 def gemm_split(A, B, C, alpha: float = 1.0, beta: float = 0.0, algo: int = SPLIT_I8,
                slices: int | None = None, workspace=None, stream=None, cfg: int = -1):
     """C <- alpha*A@B + beta*C through the split-precision path

@@ -404,6 +404,11 @@ int mg_split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, cons
 
 int mg_split_num_cfgs(void) { return split_num_cfgs(); }
 
+int mg_release_cached_memory(void) {
+  clear_error();
+  return release_workspace_pools();
+}
+
 int mg_gemm_split_cfg(int algo, int slices, int cfg, int64_t m, int64_t n, int64_t k,
                       double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
                       double beta, double *C, int64_t ldc, void *workspace,

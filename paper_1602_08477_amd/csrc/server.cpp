@@ -323,12 +323,6 @@ int server_create(const mg_server_opts *o, Server **out) {
       return MG_ERR_HIP;
     }
   }
-  // Keep freed stream-ordered allocations (split workspaces) cached.
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, S->device) == hipSuccess) {
-    uint64_t thr = UINT64_MAX;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-  }
   S->sched = std::thread(scheduler_loop, S);
   for (Lane &L : S->lanes) L.waiter = std::thread(waiter_loop, S, &L);
   *out = S;

@@ -53,11 +53,16 @@ int gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double alp
                const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
                double *C, int64_t ldc, void *ws, int64_t ws_bytes, hipStream_t s, int cfg = -1);
 
-// The same with a workspace from HIP's stream-ordered allocator on `s`, of
+// The same with a workspace from the library's stream-ordered pool on `s`, of
 // the size the picked division needs (see split_pick_cfg for `latency`).
 int gemm_split_pooled(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
                       const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
                       double *C, int64_t ldc, hipStream_t s, bool latency = true);
+
+// The library's stream-ordered pool for split workspaces on the current
+// device (freed blocks are kept for reuse), and a trim of every such pool.
+int workspace_pool(hipMemPool_t *out);
+int release_workspace_pools();
 
 // Many independent FP64 problems (validated descriptors) in one set of
 // launches: per-problem workspaces in one stream-ordered allocation, batched

@@ -184,6 +184,61 @@ __device__ __forceinline__ void slice_rows_exp_body(const double *A, int64_t lda
   }
 }
 
+// The same for rows of at most 1024 (padded) k with one wavefront per row:
+// a lane holds quads lane, lane + 64, lane + 128, lane + 192 in registers,
+// and the row's exponent is a wavefront reduction.  Row `i`.
+template <int ESZ>
+__device__ __forceinline__ void slice_rows_wave_body(const double *A, int64_t lda, int m, int k,
+                                                     int mp, int64_t kp, int *E, int s, int bits,
+                                                     unsigned char *out, int i) {
+  constexpr int QPT = 4;
+  const int lane = threadIdx.x & 63;
+  const bool live = i < m;
+  const double *row = A + (int64_t)(live ? i : 0) * lda;
+  const int quads = (int)(kp / 4);
+  double x[QPT][4];
+  int e = INT_MIN;
+#pragma unroll
+  for (int j = 0; j < QPT; ++j) {
+    const int qd = lane + 64 * j;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int kk = qd * 4 + v;
+      const double val = (live && qd < quads && kk < k) ? row[kk] : 0.0;
+      x[j][v] = val;
+      e = max(e, exp_of(val));
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) e = max(e, __shfl_xor(e, off));
+  const int ei = (e == INT_MIN) ? 0 : e;
+  if (lane == 0) E[i] = ei;
+  const int64_t slice_bytes = (int64_t)mp * kp * ESZ;
+#pragma unroll
+  for (int j = 0; j < QPT; ++j) {
+    const int qd = lane + 64 * j;
+    if (qd >= quads) continue;
+    double r[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) r[v] = ldexp(x[j][v], -ei);
+    unsigned char *o = out + ((int64_t)i * kp + qd * 4) * ESZ;
+    for (int t = 0; t < s; ++t) {
+      int q[4];
+      slice_round<4>(r, q, bits);
+      if (ESZ == 1) {
+        const unsigned w = (q[0] & 0xff) | ((q[1] & 0xff) << 8) | ((q[2] & 0xff) << 16) |
+                           ((unsigned)(q[3] & 0xff) << 24);
+        *reinterpret_cast<unsigned *>(o + t * slice_bytes) = w;
+      } else {
+        uint2 w;
+        w.x = SlicePack<2>::bf16_bits(q[0]) | (SlicePack<2>::bf16_bits(q[1]) << 16);
+        w.y = SlicePack<2>::bf16_bits(q[2]) | (SlicePack<2>::bf16_bits(q[3]) << 16);
+        *reinterpret_cast<uint2 *>(o + t * slice_bytes) = w;
+      }
+    }
+  }
+}
+
 template <int ESZ>
 __global__ __launch_bounds__(256) void slice_rows_exp_kernel(const double *A, int64_t lda, int m,
                                                              int k, int mp, int64_t kp, int *E,
@@ -359,6 +414,54 @@ __device__ __forceinline__ void finish_tile(const SplitArgs &a, typename M::acc_
     }
     __builtin_amdgcn_sched_barrier(0);
   }
+}
+
+// The same fold and epilogue with the lane's FP64 partial sums held in
+// registers (tiles small enough to afford them): identical arithmetic in the
+// identical order, no partial-sum traffic.
+template <typename M, int FMW, int FNW>
+__device__ __forceinline__ void fold_regs(typename M::acc_t (&acc)[FMW][FNW],
+                                          i4v (&dacc)[FMW][FNW], double (&part)[FMW][FNW][4],
+                                          double sc, bool first) {
+#pragma unroll
+  for (int i = 0; i < FMW; ++i)
+#pragma unroll
+    for (int j = 0; j < FNW; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int v = M::CHUNK_STAGES > 0 ? dacc[i][j][r] : (int)acc[i][j][r];
+        part[i][j][r] = fma((double)v, sc, first ? 0.0 : part[i][j][r]);
+        dacc[i][j][r] = 0;
+        if (M::CHUNK_STAGES == 0) acc[i][j][r] = 0;
+      }
+}
+
+template <typename M, int FMW, int FNW>
+__device__ __forceinline__ void finish_regs(const SplitArgs &a, typename M::acc_t (&acc)[FMW][FNW],
+                                            i4v (&dacc)[FMW][FNW],
+                                            const double (&part)[FMW][FNW][4], bool only, int row0,
+                                            int col0) {
+  const double sc = ldexp(1.0, -a.bits * (a.s + 1));
+#pragma unroll
+  for (int i = 0; i < FMW; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row0 + 16 * i + r;
+      const bool row_ok = row < a.m;
+      const int er = row_ok ? a.E[row] : 0;
+      double *crow = a.C + (int64_t)(row_ok ? row : 0) * a.ldc;
+#pragma unroll
+      for (int j = 0; j < FNW; ++j) {
+        const int col = col0 + 16 * j;
+        const int v = M::CHUNK_STAGES > 0 ? dacc[i][j][r] : (int)acc[i][j][r];
+        const double fin = fma((double)v, sc, only ? 0.0 : part[i][j][r]);
+        if (!row_ok || col >= a.n) continue;
+        const double prod = ldexp(fin, er + a.F[col]);
+        double o = __dmul_rn(a.alpha, prod);
+        if (a.beta != 0.0) o = __dadd_rn(o, __dmul_rn(a.beta, crow[col]));
+        crow[col] = o;
+      }
+    }
 }
 
 // Work divisions of the product kernel: WGM x WGN wavefronts, each owning
@@ -549,7 +652,8 @@ __device__ __forceinline__ void dma16(const unsigned char *src, unsigned char *l
 // One output tile (m0, n0) of the product: every slice pair over every k
 // stage, the folds, the epilogue.  `plane0`: the tile's BM*BN partial sums.
 // `a.seg_stages` and `a.total_stages` count SB-byte stages here.
-template <int ALGO, int WGM, int WGN, int FMW, int FNW, int NS, int SB>
+// REG: partial sums in registers (plane0 unused) instead of the plane.
+template <int ALGO, int WGM, int WGN, int FMW, int FNW, int NS, int SB, bool REG = false>
 __device__ __forceinline__ void split_dma_tile(const SplitArgs &a, int m0, int n0, double *plane0,
                                                unsigned char *lds) {
   typedef SplitMma<ALGO> M;
@@ -578,7 +682,8 @@ __device__ __forceinline__ void split_dma_tile(const SplitArgs &a, int m0, int n
     const int row = S::RPI * (wave * S::IB + u) + lane / S::CPR;
     bsrc[u] = (int64_t)(n0 + row) * a.kp_bytes + swz_chunk<SB>(row, lane % S::CPR) * 16;
   }
-  double *plane = plane0 + tid;  // this lane's partial sums
+  double *plane = REG ? nullptr : plane0 + tid;  // this lane's partial sums (plane)
+  double part[REG ? FMW : 1][REG ? FNW : 1][4];   // (registers)
 
   auto issue = [&](const Step &x, int stage) {
     const int64_t koff = (int64_t)(x.seg * a.seg_stages + x.st) * SB;
@@ -655,16 +760,22 @@ __device__ __forceinline__ void split_dma_tile(const SplitArgs &a, int m0, int n
             acc[i][j][r] = 0;
           }
     }
-    if (t + 1 < T && seg_last && cur.p == pmax_of(cur.d, a.s))
-      fold_partials<M, FMW, FNW, S::THREADS>(acc, dacc, plane, ldexp(1.0, -a.bits * cur.d),
-                                             cur.seg == 0 && cur.d == 2);
+    if (t + 1 < T && seg_last && cur.p == pmax_of(cur.d, a.s)) {
+      const double sc = ldexp(1.0, -a.bits * cur.d);
+      const bool first = cur.seg == 0 && cur.d == 2;
+      if constexpr (REG) fold_regs<M, FMW, FNW>(acc, dacc, part, sc, first);
+      else fold_partials<M, FMW, FNW, S::THREADS>(acc, dacc, plane, sc, first);
+    }
     advance(cur, a);
   }
 
   // Last diagonal of the last segment, then the epilogue.
   const bool only = a.s == 1 && a.seg_stages >= a.total_stages;  // a single fold in all
-  finish_tile<M, FMW, FNW, S::THREADS>(a, acc, dacc, plane, only, m0 + wm0 + 4 * g,
-                                       n0 + wn0 + l16);
+  if constexpr (REG)
+    finish_regs<M, FMW, FNW>(a, acc, dacc, part, only, m0 + wm0 + 4 * g, n0 + wn0 + l16);
+  else
+    finish_tile<M, FMW, FNW, S::THREADS>(a, acc, dacc, plane, only, m0 + wm0 + 4 * g,
+                                         n0 + wn0 + l16);
 }
 
 template <int ALGO, int WGM, int WGN, int FMW, int FNW, int NS, int SB>
@@ -980,30 +1091,34 @@ int launch_split(int algo, const SplitArgs &a, const SplitLayout &L, hipStream_t
 
 // ---------------------------------------------------------------------------
 // Batched split GEMM: many independent problems in one set of launches.
-// Every problem keeps the single-problem workspace layout, all of them in one
-// allocation.  The preparation launches run one grid over the blocks of all
-// problems (a workgroup finds its problem by binary search over the block
-// prefix sums); the product launch runs one workgroup per output tile of
-// every problem, longest k first, with the tile code of the fused 128x128
-// division -- so each result is the one a single call gives, bit for bit.
-// Only tiles that hold outputs are run, and only the rows of A / columns of
-// B those tiles read are sliced.
+// The preparation launches run one grid over the blocks of all problems (a
+// workgroup finds its problem by binary search over the block prefix sums);
+// the product launch runs one workgroup per 64x64 output tile of every
+// problem, longest k first, with the DMA ring's tile code and the FP64
+// partial sums in registers -- the same slices, integer products and folds
+// in the same order as the single-problem divisions, so each result is the
+// one a single call gives, bit for bit.  Per problem the workspace holds
+// only what those tiles read: E and F, and slices of A and B padded to 64
+// rows / columns and 128 k.
 struct SplitPrepDesc {
   const double *A, *B;
   int64_t lda, ldb, kp;
   int m, n, k, mp, np;
-  int nr;      // columns of B the product tiles read: n rounded up to 128
+  int nr;      // columns of B the product tiles read: n rounded up to the tile
   int cx, cy;  // column-exponent blocks: cx blocks of 256 columns x cy k-chunk strides
+  int rpb;     // rows of A per block: 4 (one per wavefront, kp <= 1024) or 1
   int *E, *F;
   unsigned char *As, *Bs;
 };
 
 struct SplitTileRec {
-  int prob, m0, n0, local;  // local: the tile's index in its problem's partial-sum region
+  int prob, m0, n0, pad;
 };
 
-// 128x128 tile on 8 wavefronts, 2-stage ring of 128 bytes (division 12).
-typedef SplitDmaShape<2, 4, 4, 2, 2, 128> BatchShape;
+// 64x64 tile on 4 wavefronts (32x32 each), 3-stage ring of 128 bytes: three
+// workgroups per CU.
+typedef SplitDmaShape<2, 2, 2, 2, 3, 128> BatchShape;
+constexpr int kBatchWavesPerSimd = 3;
 
 // Problem that owns block b of a batched launch: the last i with first[i] <= b.
 __device__ __forceinline__ int batch_problem(const int *first, int count, int b) {
@@ -1031,8 +1146,13 @@ __global__ __launch_bounds__(256) void batched_exp_rows_kernel(const SplitPrepDe
   const int i = batch_problem(first, count, blockIdx.x);
   const SplitPrepDesc &q = d[i];
   const int lb = blockIdx.x - first[i], ncol = q.cx * q.cy;
-  if (lb < ncol) col_exp_body(q.B, q.ldb, q.k, q.n, q.F, lb % q.cx, lb / q.cx, q.cy);
-  else slice_rows_exp_body<ESZ>(q.A, q.lda, q.m, q.k, q.mp, q.kp, q.E, s, bits, q.As, lb - ncol);
+  if (lb < ncol)
+    col_exp_body(q.B, q.ldb, q.k, q.n, q.F, lb % q.cx, lb / q.cx, q.cy);
+  else if (q.rpb == 1)
+    slice_rows_exp_body<ESZ>(q.A, q.lda, q.m, q.k, q.mp, q.kp, q.E, s, bits, q.As, lb - ncol);
+  else
+    slice_rows_wave_body<ESZ>(q.A, q.lda, q.m, q.k, q.mp, q.kp, q.E, s, bits, q.As,
+                              (lb - ncol) * 4 + (int)(threadIdx.x >> 6));
 }
 
 template <int ESZ>
@@ -1046,13 +1166,12 @@ __global__ __launch_bounds__(256) void batched_slice_cols_kernel(const SplitPrep
 }
 
 template <int ALGO>
-__global__ __launch_bounds__(BatchShape::THREADS, BatchShape::MINW) void split_batched_kernel(
+__global__ __launch_bounds__(BatchShape::THREADS, kBatchWavesPerSimd) void split_batched_kernel(
     const SplitArgs *args, const SplitTileRec *recs) {
   extern __shared__ __align__(16) unsigned char lds[];
   const SplitTileRec r = recs[blockIdx.x];
   const SplitArgs a = args[r.prob];
-  split_dma_tile<ALGO, 2, 4, 4, 2, 2, 128>(
-      a, r.m0, r.n0, a.P + (int64_t)r.local * (BatchShape::BM * BatchShape::BN), lds);
+  split_dma_tile<ALGO, 2, 2, 2, 2, 3, 128, true>(a, r.m0, r.n0, nullptr, lds);
 }
 
 template <int ALGO>
@@ -1348,6 +1467,72 @@ int64_t split_workspace_bytes(int algo, int slices, int64_t m, int64_t n, int64_
   return split_ws_needed(L, split_pick_cfg(algo, L.mp, L.np, latency));
 }
 
+namespace {
+
+constexpr int kMaxPoolDevices = 64;
+std::mutex g_pool_mu;
+hipMemPool_t g_pools[kMaxPoolDevices] = {};
+
+}  // namespace
+
+// The library's stream-ordered pool for split workspaces on the current
+// device: created on first use, it keeps freed blocks for reuse (no release
+// threshold) instead of returning them to the device at every
+// synchronization; mg_release_cached_memory trims it.  The caller's default
+// pool is left as it is.
+int workspace_pool(hipMemPool_t *out) {
+  int dev = 0;
+  MG_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxPoolDevices) {
+    set_error("device %d beyond the %d the library supports", dev, kMaxPoolDevices);
+    return MG_ERR_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if (g_pools[dev] == nullptr) {
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    MG_HIP_TRY(hipMemPoolCreate(&pool, &props));
+    uint64_t thr = UINT64_MAX;
+    const hipError_t e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    if (e != hipSuccess) {
+      (void)hipMemPoolDestroy(pool);
+      set_error("hipMemPoolSetAttribute failed: %s", hipGetErrorString(e));
+      return MG_ERR_HIP;
+    }
+    g_pools[dev] = pool;
+  }
+  *out = g_pools[dev];
+  return MG_OK;
+}
+
+int release_workspace_pools() {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  for (int d = 0; d < kMaxPoolDevices; ++d)
+    if (g_pools[d] != nullptr) MG_HIP_TRY(hipMemPoolTrimTo(g_pools[d], 0));
+  return MG_OK;
+}
+
+namespace {
+
+// Stream-ordered workspace from the library's pool.
+int pool_alloc(void **p, int64_t bytes, hipStream_t s) {
+  hipMemPool_t pool = nullptr;
+  int rc = workspace_pool(&pool);
+  if (rc != MG_OK) return rc;
+  const hipError_t e = hipMallocFromPoolAsync(p, (size_t)bytes, pool, s);
+  if (e != hipSuccess) {
+    set_error("workspace allocation (%lld bytes) failed: %s", (long long)bytes,
+              hipGetErrorString(e));
+    return MG_ERR_NO_MEMORY;
+  }
+  return MG_OK;
+}
+
+}  // namespace
+
 int gemm_split_pooled(int algo, int slices, int64_t m, int64_t n, int64_t k, double alpha,
                       const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
                       double *C, int64_t ldc, hipStream_t s, bool latency) {
@@ -1360,11 +1545,8 @@ int gemm_split_pooled(int algo, int slices, int64_t m, int64_t n, int64_t k, dou
   const int cfg = split_pick_cfg(algo, L.mp, L.np, latency);
   const int64_t bytes = split_ws_needed(L, cfg);
   void *ws = nullptr;
-  hipError_t e = hipMallocAsync(&ws, (size_t)bytes, s);
-  if (e != hipSuccess) {
-    set_error("hipMallocAsync(%lld bytes) failed: %s", (long long)bytes, hipGetErrorString(e));
-    return MG_ERR_NO_MEMORY;
-  }
+  rc = pool_alloc(&ws, bytes, s);
+  if (rc != MG_OK) return rc;
   rc = gemm_split(algo, slices, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ws, bytes, s, cfg);
   MG_HIP_TRY(hipFreeAsync(ws, s));
   return rc;
@@ -1427,15 +1609,32 @@ int gemm_split_batched(int algo, int slices, int64_t count, const mg_problem *pr
     set_error("too many problems in one batch");
     return MG_ERR_INVALID_ARG;
   }
-  std::vector<SplitLayout> L((size_t)nl);
+  // Per-problem workspace: E [mr], F [nr], A slices [s][mr][kp], B slices
+  // [s][nr][kp] (B transposed), mr / nr = m / n rounded up to the tile.
+  struct BLayout {
+    int64_t mr, nr, kp, e_off, f_off, a_off, b_off;
+  };
+  const int64_t esz = algo == MG_SPLIT_BF16 ? 2 : 1;
+  std::vector<BLayout> L((size_t)nl);
   std::vector<int64_t> woff((size_t)nl);
   int64_t wbytes = 0;
   for (int j = 0; j < nl; ++j) {
     const mg_problem &q = probs[live[(size_t)j]];
-    int rc = split_layout(algo, slices, q.m, q.n, q.k, &L[(size_t)j]);
-    if (rc != MG_OK) return rc;
+    BLayout &l = L[(size_t)j];
+    l.mr = round_up(q.m, (int64_t)S::BM);
+    l.nr = round_up(q.n, (int64_t)S::BN);
+    l.kp = round_up(q.k, (int64_t)kSplitTileK);
+    int64_t off = 0;
+    l.e_off = off;
+    off = round_up(off + 4 * l.mr, 256);
+    l.f_off = off;
+    off = round_up(off + 4 * l.nr, 256);
+    l.a_off = off;
+    off = round_up(off + slices * l.mr * l.kp * esz, 256);
+    l.b_off = off;
+    off = round_up(off + slices * l.nr * l.kp * esz, 256);
     woff[(size_t)j] = wbytes;
-    wbytes += split_ws_needed(L[(size_t)j], 12);  // the fused divisions' workspace
+    wbytes += off;
   }
   // Longest k first: the costliest tiles start first and the short ones
   // fill in behind them.
@@ -1453,11 +1652,11 @@ int gemm_split_batched(int algo, int slices, int64_t count, const mg_problem *pr
   int64_t blocks[3] = {0, 0, 0};
   for (int j = 0; j < nl; ++j) {
     const mg_problem &q = probs[live[(size_t)j]];
-    const SplitLayout &l = L[(size_t)j];
-    const int64_t mr = round_up(q.m, (int64_t)S::BM), nr = round_up(q.n, (int64_t)S::BN);
+    const BLayout &l = L[(size_t)j];
     const int64_t nchunks = ceil_div(q.k, kColRows);
     const int64_t cx = ceil_div(q.n, 256), cy = std::min<int64_t>(nchunks, 256);
-    const int64_t nb[3] = {ceil_div(nr, 256), cx * cy + mr, (nr / 64) * (l.kp / 64)};
+    const int64_t rpb = l.kp <= 1024 ? 4 : 1;
+    const int64_t nb[3] = {ceil_div(l.nr, 256), cx * cy + l.mr / rpb, (l.nr / 64) * (l.kp / 64)};
     for (int w = 0; w < 3; ++w) {
       first[(size_t)w * (nl + 1) + j] = (int)blocks[w];
       blocks[w] += nb[w];
@@ -1469,13 +1668,10 @@ int gemm_split_batched(int algo, int slices, int64_t count, const mg_problem *pr
   }
   for (int w = 0; w < 3; ++w) first[(size_t)w * (nl + 1) + nl] = (int)blocks[w];
   for (int j : ord) {
-    const mg_problem &q = probs[live[(size_t)j]];
-    const SplitLayout &l = L[(size_t)j];
-    const int64_t tm = ceil_div(q.m, (int64_t)S::BM), tn = ceil_div(q.n, (int64_t)S::BN);
-    const int64_t tn_all = l.np / S::BN;
-    for (int64_t a = 0; a < tm; ++a)
-      for (int64_t b = 0; b < tn; ++b)
-        recs.push_back(SplitTileRec{j, (int)(a * S::BM), (int)(b * S::BN), (int)(a * tn_all + b)});
+    const BLayout &l = L[(size_t)j];
+    for (int64_t a = 0; a < l.mr / S::BM; ++a)
+      for (int64_t b = 0; b < l.nr / S::BN; ++b)
+        recs.push_back(SplitTileRec{j, (int)(a * S::BM), (int)(b * S::BN), 0});
   }
   if (recs.size() * S::THREADS > (size_t)UINT32_MAX) {
     set_error("split batch too large for one dispatch");
@@ -1488,20 +1684,16 @@ int gemm_split_batched(int algo, int slices, int64_t count, const mg_problem *pr
   const size_t meta = align256(o_recs + recs.size() * sizeof(SplitTileRec));
 
   void *dev = nullptr;
-  hipError_t e = hipMallocAsync(&dev, (size_t)wbytes + meta, s);
-  if (e != hipSuccess) {
-    set_error("hipMallocAsync(%lld bytes) failed: %s", (long long)(wbytes + (int64_t)meta),
-              hipGetErrorString(e));
-    return MG_ERR_NO_MEMORY;
-  }
+  int rc = pool_alloc(&dev, wbytes + (int64_t)meta, s);
+  if (rc != MG_OK) return rc;
   unsigned char *w = static_cast<unsigned char *>(dev);
   const int bits = split_bits(algo);
   for (int j = 0; j < nl; ++j) {
     const mg_problem &q = probs[live[(size_t)j]];
-    const SplitLayout &l = L[(size_t)j];
+    const BLayout &l = L[(size_t)j];
     unsigned char *base = w + woff[(size_t)j];
     SplitArgs &a = args[(size_t)j];
-    a.P = reinterpret_cast<double *>(base + l.p_off);
+    a.P = nullptr;  // partial sums stay in registers
     a.Q = nullptr;
     a.As = base + l.a_off;
     a.Bs = base + l.b_off;
@@ -1511,9 +1703,9 @@ int gemm_split_batched(int algo, int slices, int64_t count, const mg_problem *pr
     a.ldc = q.ldc;
     a.m = (int)q.m;
     a.n = (int)q.n;
-    a.mp = (int)l.mp;
-    a.np = (int)l.np;
-    a.kp_bytes = l.kp * l.elem_bytes;
+    a.mp = (int)l.mr;  // slice pitches
+    a.np = (int)l.nr;
+    a.kp_bytes = l.kp * esz;
     a.s = slices;
     a.bits = bits;
     a.total_stages = (int)(a.kp_bytes / kStageBytes);
@@ -1529,11 +1721,12 @@ int gemm_split_batched(int algo, int slices, int64_t count, const mg_problem *pr
     d.m = (int)q.m;
     d.n = (int)q.n;
     d.k = (int)q.k;
-    d.mp = (int)l.mp;
-    d.np = (int)l.np;
-    d.nr = (int)round_up(q.n, (int64_t)S::BN);
+    d.mp = (int)l.mr;
+    d.np = (int)l.nr;
+    d.nr = (int)l.nr;
     d.cx = (int)ceil_div(q.n, 256);
     d.cy = (int)std::min<int64_t>(ceil_div(q.k, kColRows), 256);
+    d.rpb = l.kp <= 1024 ? 4 : 1;
     d.E = reinterpret_cast<int *>(base + l.e_off);
     d.F = reinterpret_cast<int *>(base + l.f_off);
     d.As = base + l.a_off;
@@ -1546,8 +1739,7 @@ int gemm_split_batched(int algo, int slices, int64_t count, const mg_problem *pr
   std::memcpy(h + o_first, first.data(), first.size() * sizeof(int));
   std::memcpy(h + o_recs, recs.data(), recs.size() * sizeof(SplitTileRec));
   unsigned char *dm = w + wbytes;
-  int rc = MG_OK;
-  e = hipMemcpyAsync(dm, h, meta, hipMemcpyHostToDevice, s);
+  hipError_t e = hipMemcpyAsync(dm, h, meta, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) {
     set_error("hipMemcpyAsync failed: %s", hipGetErrorString(e));
     rc = MG_ERR_HIP;

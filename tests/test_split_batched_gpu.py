@@ -133,13 +133,15 @@ def test_batched_split_config4_shapes(kind):
 
 def test_batched_split_repeat_reads_current_operands():
     """Nothing is cached between split batches: a second call with changed
-    operands in the same buffers gives the new product."""
+    operands in the same buffers gives the new product, also after the
+    workspace pool was trimmed."""
     shapes = [(70, 90, 110), (200, 130, 60)]
     views, flats, probs = make_batch(778, shapes, beta=0.0)
     mg.gemm_batched(probs, dtype=mg.F64, algo=mg.SPLIT_I8)
     torch.cuda.synchronize()
     flats["A"].mul_(2.0)
-    mg.gemm_batched(probs, dtype=mg.F64, algo=mg.SPLIT_I8)
+    mg.release_cached_memory()  # the workspace pool gives its blocks back; the next call
+    mg.gemm_batched(probs, dtype=mg.F64, algo=mg.SPLIT_I8)  # allocates afresh
     torch.cuda.synchronize()
     for (A, B, C) in views:
         want = osplit.split_gemm(1.0, A.cpu().numpy(), B.cpu().numpy(), 0.0, None, 7, "i8")

@@ -547,6 +547,23 @@ def bench_batched(steps):
         torch.cuda.synchronize()
         out[name]["rel_fro_err_max_all_problems"] = float(
             f"{batched_oracle_error(shapes, offs, flats, C_init):.3e}")
+        if dt == torch.float64:
+            # the same problems through the batched split-precision path
+            # (mg_gemm_batched with MG_SPLIT_I8 / BF16; each call builds its
+            # descriptors and workspace), with every problem's error against
+            # the oracle
+            for sname, salgo in (("split_i8", mg.SPLIT_I8), ("split_bf16", mg.SPLIT_BF16)):
+                flats["C"].copy_(C_init)
+                (per_s,) = time_interleaved(
+                    [lambda: mg.gemm_batched(probs, dtype=code, algo=salgo)], steps, 3, stream)
+                ms_s = float(np.median(per_s))
+                flats["C"].copy_(C_init)
+                mg.gemm_batched(probs, dtype=code, algo=salgo)
+                torch.cuda.synchronize()
+                out[name][sname] = {
+                    "ms": round(ms_s, 4), "fp64_equivalent_tflops": round(flop / ms_s / 1e9, 2),
+                    "rel_fro_err_max_all_problems": float(
+                        f"{batched_oracle_error(shapes, offs, flats, C_init):.3e}")}
         del C_init
         if dt == torch.float64:
             # context: the same problems with every row pitch rounded up to an

@@ -64,6 +64,12 @@ const char *mg_last_error(void);
 /* Library ABI version (major*10000 + minor*100 + patch). */
 int mg_version(void);
 
+/* Build variant: MG_BUILD_LDS_POISON is set in the debug build whose kernels
+ * fill every LDS stage with 0xFF bytes before refilling it (race checks; the
+ * release build returns 0). */
+#define MG_BUILD_LDS_POISON 1
+int mg_build_flags(void);
+
 /* ------------------------------------------------------------ plain GEMM --
  * mg_gemm: C <- alpha*A*B + beta*C (Section 4.2 problem statement).
  *   dtype  MG_F64 (algo MG_NATIVE, MG_SPLIT_I8 or MG_SPLIT_BF16; the split
@@ -323,9 +329,11 @@ int mg_plan_destroy(mg_plan *plan);
  * the split-precision method of mg_gemm on every problem, with the default
  * slice count, in four launches for the whole batch -- exponents and slices
  * of all problems (three preparation grids), then one grid of 64x64 output
- * tiles over all problems, longest k first, with the FP64 partial sums in
- * registers (Section 3.3: independent grids of one device run concurrently;
- * here they share one launch).  The per-problem workspaces (exponents and
+ * tiles over all problems, longest k first, each tile staging every slice of
+ * its rows of A and columns of B per k stage and forming all slice pairs
+ * from them, with the diagonal sums and FP64 partial sums in registers
+ * (Section 3.3: independent grids of one device run concurrently; here they
+ * share one launch).  The per-problem workspaces (exponents and
  * slices padded to 64 rows / columns and 128 k, in one allocation from the
  * library's workspace pool, freed on `stream` after the batch) and the
  * descriptors are built per call; nothing is kept.  Each result equals

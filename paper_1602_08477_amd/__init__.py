@@ -15,7 +15,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmg.so")
+# MG_LIBRARY selects another build of the library (the LDS-poison debug
+# build, libmg_poison.so, for race checks); default: the release build.
+LIB_PATH = os.environ.get("MG_LIBRARY") or os.path.join(_HERE, "libmg.so")
 
 # status codes (include/mg.h)
 NAIVE_CFG = 25  # the one-output-per-lane work division (MG_NAIVE_CFG)
@@ -33,6 +35,7 @@ F32 = 1
 NATIVE = 0
 SPLIT_I8 = 1
 SPLIT_BF16 = 2
+BUILD_LDS_POISON = 1
 
 
 class MgError(RuntimeError):
@@ -236,6 +239,11 @@ def split_prepare(algo: int, slices: int, A, B, workspace, stream=None):
 
 def split_num_cfgs() -> int:
     return lib().mg_split_num_cfgs()
+
+
+def build_flags() -> int:
+    """mg_build_flags: 1 (MG_BUILD_LDS_POISON) for the LDS-poison debug build."""
+    return lib().mg_build_flags()
 
 
 def release_cached_memory() -> None:

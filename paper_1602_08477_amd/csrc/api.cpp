@@ -227,6 +227,14 @@ const char *mg_last_error(void) { return g_err; }
 
 int mg_version(void) { return 10100; }
 
+int mg_build_flags(void) {
+#ifdef MG_LDS_POISON
+  return MG_BUILD_LDS_POISON;
+#else
+  return 0;
+#endif
+}
+
 int mg_num_tile_cfgs(void) { return num_tile_cfgs(); }
 
 int mg_tile_cfg_info(int dtype, int cfg, int *bm, int *bn, int *bk, int *threads) {
@@ -581,7 +589,7 @@ int mg_gemm_batched(int dtype, int algo, int64_t count, const mg_problem *probs,
   if (count == 0) return MG_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (algo != MG_NATIVE)  // built per call (its workspace is per call too)
-    return gemm_split_batched(algo, split_default_slices(algo), count, probs, s);
+    return gemm_split_batched(algo, count, probs, s);
   int dev = 0;
   MG_HIP_TRY(hipGetDevice(&dev));
   const uint64_t h = hash_problems(dtype, count, probs);

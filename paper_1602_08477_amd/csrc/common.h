@@ -33,6 +33,27 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 typedef int i4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
+// ------------------------------------------------- LDS poison (debug) --
+// Built with -DMG_LDS_POISON (the debug library variant), every LDS stage is
+// filled with 0xFF bytes (NaN as FP64 / FP32 / BF16, -1 as INT8) before it is
+// (re)filled, then the LDS writes are waited for and the workgroup
+// synchronises (no wait on vector memory, so loads in flight stay in flight).
+// A read of a stage before its data has landed, or of bytes no load writes,
+// then changes the result; the normal build compiles this to nothing.
+#ifdef MG_LDS_POISON
+__device__ __forceinline__ void lds_poison(void *p, int bytes) {
+  typedef __attribute__((address_space(3))) int lds_int;
+  lds_int *q = (lds_int *)(__attribute__((address_space(3))) void *)p;
+  for (int o = (int)threadIdx.x; o < bytes / 4; o += (int)blockDim.x) q[o] = -1;
+  // lgkmcnt(0); vmcnt and expcnt at their maxima (not waited for)
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_s_barrier();
+}
+#define MG_LDS_POISON_STAGE(p, bytes) ::mg::lds_poison((p), (bytes))
+#else
+#define MG_LDS_POISON_STAGE(p, bytes) ((void)0)
+#endif
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 

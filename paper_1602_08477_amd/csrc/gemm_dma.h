@@ -325,6 +325,7 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs<T> &g, int m0, int 
     else zero_kcols(Bs, BN, kvalid);
   };
 
+  MG_LDS_POISON_STAGE(lds, NS * S::STAGE);
 #pragma unroll
   for (int q = 0; q < NS - 1; ++q)
     if (q < KT) issue(q);
@@ -332,7 +333,10 @@ __device__ __forceinline__ void gemm_dma_tile(const GemmArgs<T> &g, int m0, int 
     // step kt has landed once only the later issued steps may be pending
     dma_wait_steps<DPS, NS>(min(KT - 1, kt + NS - 2) - kt);
     __builtin_amdgcn_s_barrier();
-    if (kt + NS - 1 < KT) issue(kt + NS - 1);
+    if (kt + NS - 1 < KT) {
+      MG_LDS_POISON_STAGE(lds + ((kt + NS - 1) % NS) * S::STAGE, S::STAGE);
+      issue(kt + NS - 1);
+    }
     unsigned char *As = lds + (kt % NS) * S::STAGE;
     unsigned char *Bs = As + S::A_BYTES;
     const int kvalid = g.k - kt * BK;

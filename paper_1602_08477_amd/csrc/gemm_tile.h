@@ -407,6 +407,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &g, int m0, int n0, 
     for (int j = 0; j < S::FN; ++j) acc[i][j] = Acc{};
 
   const int KT = (g.k + BK - 1) / BK;
+  MG_LDS_POISON_STAGE(smem, 2 * S::STAGE * (int)sizeof(T));
   if (KT > 0) {
     load_tiles(0);
     store_tiles(0);
@@ -414,6 +415,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T> &g, int m0, int n0, 
   __syncthreads();
   for (int kt = 0; kt < KT; ++kt) {
     const int cur = kt & 1;
+    // the other buffer is refilled after this step's products
+    MG_LDS_POISON_STAGE(smem + (cur ^ 1) * S::STAGE, S::STAGE * (int)sizeof(T));
     if (kt + 1 < KT) load_tiles(kt + 1);
     const T *As = smem + cur * S::STAGE;
     const T *Bs = As + S::A_STAGE;

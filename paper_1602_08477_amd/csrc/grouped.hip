@@ -456,6 +456,8 @@ __device__ __forceinline__ void gd_run_tile(GdLoader<T> &ld, const GTileRec<T> &
   for (int kt = 0; kt < KT; ++kt) {
     gd_wait_next(ld.q1);
     __builtin_amdgcn_s_barrier();
+    // the stage the loader refills next (consumed in the previous step)
+    MG_LDS_POISON_STAGE(ld.lds + (ld.li % kGdNS) * kGdStage, kGdStage);
     const int cnew = ld.issue();
     const unsigned char *As = ld.lds + (t % kGdNS) * kGdStage;
     const unsigned char *Bs = As + kGdStageA;
@@ -491,6 +493,7 @@ __global__ __launch_bounds__(kTileThreads, 3) void grouped_dma_kernel(
   ld.lkt = 0;
   ld.li = 0;
   ld.lr = -1;
+  MG_LDS_POISON_STAGE(lds, kGdNS * kGdStage);
   ld.next_tile();  // first tile with k-steps
   ld.q0 = ld.issue();
   ld.q1 = ld.issue();

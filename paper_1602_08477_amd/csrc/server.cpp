@@ -190,8 +190,7 @@ void launch_batch(Server *S, Lane &L, int64_t batch_id) {
     for (Req *q : L.batch)
       if (q->r.algo == algo) ps.push_back(q->r.p);
     if (ps.empty()) continue;
-    const int r2 = gemm_split_batched(algo, split_default_slices(algo), (int64_t)ps.size(),
-                                      ps.data(), L.s);
+    const int r2 = gemm_split_batched(algo, (int64_t)ps.size(), ps.data(), L.s);
     if (r2 != MG_OK)
       for (Req *q : L.batch)
         if (q->r.algo == algo) q->res.status = r2;

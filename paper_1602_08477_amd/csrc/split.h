@@ -65,10 +65,10 @@ int workspace_pool(hipMemPool_t *out);
 int release_workspace_pools();
 
 // Many independent FP64 problems (validated descriptors) in one set of
-// launches: per-problem workspaces in one stream-ordered allocation, batched
-// preparation, one product launch over the output tiles of all problems.
-// Each result equals a single call's bit for bit.
-int gemm_split_batched(int algo, int slices, int64_t count, const mg_problem *probs,
-                       hipStream_t s);
+// launches, at the default slice count: per-problem workspaces in one
+// allocation from the workspace pool, batched preparation, one product
+// launch over the 64x64 output tiles of all problems.  Each result equals a
+// single call's bit for bit.
+int gemm_split_batched(int algo, int64_t count, const mg_problem *probs, hipStream_t s);
 
 }  // namespace mg

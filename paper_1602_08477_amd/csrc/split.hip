@@ -416,54 +416,6 @@ __device__ __forceinline__ void finish_tile(const SplitArgs &a, typename M::acc_
   }
 }
 
-// The same fold and epilogue with the lane's FP64 partial sums held in
-// registers (tiles small enough to afford them): identical arithmetic in the
-// identical order, no partial-sum traffic.
-template <typename M, int FMW, int FNW>
-__device__ __forceinline__ void fold_regs(typename M::acc_t (&acc)[FMW][FNW],
-                                          i4v (&dacc)[FMW][FNW], double (&part)[FMW][FNW][4],
-                                          double sc, bool first) {
-#pragma unroll
-  for (int i = 0; i < FMW; ++i)
-#pragma unroll
-    for (int j = 0; j < FNW; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int v = M::CHUNK_STAGES > 0 ? dacc[i][j][r] : (int)acc[i][j][r];
-        part[i][j][r] = fma((double)v, sc, first ? 0.0 : part[i][j][r]);
-        dacc[i][j][r] = 0;
-        if (M::CHUNK_STAGES == 0) acc[i][j][r] = 0;
-      }
-}
-
-template <typename M, int FMW, int FNW>
-__device__ __forceinline__ void finish_regs(const SplitArgs &a, typename M::acc_t (&acc)[FMW][FNW],
-                                            i4v (&dacc)[FMW][FNW],
-                                            const double (&part)[FMW][FNW][4], bool only, int row0,
-                                            int col0) {
-  const double sc = ldexp(1.0, -a.bits * (a.s + 1));
-#pragma unroll
-  for (int i = 0; i < FMW; ++i)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = row0 + 16 * i + r;
-      const bool row_ok = row < a.m;
-      const int er = row_ok ? a.E[row] : 0;
-      double *crow = a.C + (int64_t)(row_ok ? row : 0) * a.ldc;
-#pragma unroll
-      for (int j = 0; j < FNW; ++j) {
-        const int col = col0 + 16 * j;
-        const int v = M::CHUNK_STAGES > 0 ? dacc[i][j][r] : (int)acc[i][j][r];
-        const double fin = fma((double)v, sc, only ? 0.0 : part[i][j][r]);
-        if (!row_ok || col >= a.n) continue;
-        const double prod = ldexp(fin, er + a.F[col]);
-        double o = __dmul_rn(a.alpha, prod);
-        if (a.beta != 0.0) o = __dadd_rn(o, __dmul_rn(a.beta, crow[col]));
-        crow[col] = o;
-      }
-    }
-}
-
 // Work divisions of the product kernel: WGM x WGN wavefronts, each owning
 // FMW x FNW blocks of 16x16 outputs.
 template <int WGM, int WGN, int FMW, int FNW>
@@ -550,10 +502,13 @@ __global__ __launch_bounds__((SplitShape<WGM, WGN, FMW, FNW>::THREADS), MINB) vo
   const int pairs = a.s * (a.s + 1) / 2;
   const int T = pairs * a.total_stages;
   Step cur = {0, 2, 1, 0};
+  MG_LDS_POISON_STAGE(lds, 2 * STAGE);
   load(cur);
   store(0);
   __syncthreads();
   for (int t = 0; t < T; ++t) {
+    // the other buffer is refilled after this step's products
+    MG_LDS_POISON_STAGE(lds + ((t + 1) & 1) * STAGE, STAGE);
     Step nxt = cur;
     advance(nxt, a);
     if (t + 1 < T) load(nxt);
@@ -652,8 +607,7 @@ __device__ __forceinline__ void dma16(const unsigned char *src, unsigned char *l
 // One output tile (m0, n0) of the product: every slice pair over every k
 // stage, the folds, the epilogue.  `plane0`: the tile's BM*BN partial sums.
 // `a.seg_stages` and `a.total_stages` count SB-byte stages here.
-// REG: partial sums in registers (plane0 unused) instead of the plane.
-template <int ALGO, int WGM, int WGN, int FMW, int FNW, int NS, int SB, bool REG = false>
+template <int ALGO, int WGM, int WGN, int FMW, int FNW, int NS, int SB>
 __device__ __forceinline__ void split_dma_tile(const SplitArgs &a, int m0, int n0, double *plane0,
                                                unsigned char *lds) {
   typedef SplitMma<ALGO> M;
@@ -682,8 +636,7 @@ __device__ __forceinline__ void split_dma_tile(const SplitArgs &a, int m0, int n
     const int row = S::RPI * (wave * S::IB + u) + lane / S::CPR;
     bsrc[u] = (int64_t)(n0 + row) * a.kp_bytes + swz_chunk<SB>(row, lane % S::CPR) * 16;
   }
-  double *plane = REG ? nullptr : plane0 + tid;  // this lane's partial sums (plane)
-  double part[REG ? FMW : 1][REG ? FNW : 1][4];   // (registers)
+  double *plane = plane0 + tid;  // this lane's partial sums
 
   auto issue = [&](const Step &x, int stage) {
     const int64_t koff = (int64_t)(x.seg * a.seg_stages + x.st) * SB;
@@ -711,6 +664,7 @@ __device__ __forceinline__ void split_dma_tile(const SplitArgs &a, int m0, int n
   const int T = pairs * a.total_stages;
   Step cur = {0, 2, 1, 0};
   Step ld = cur;
+  MG_LDS_POISON_STAGE(lds, NS * STAGE);
   // prologue: steps 0 .. NS-2
 #pragma unroll
   for (int q = 0; q < NS - 1; ++q) {
@@ -725,6 +679,7 @@ __device__ __forceinline__ void split_dma_tile(const SplitArgs &a, int m0, int n
     else wait_vmcnt<0>();
     __builtin_amdgcn_s_barrier();
     if (t + NS - 1 < T) {
+      MG_LDS_POISON_STAGE(lds + ((t + NS - 1) % NS) * STAGE, STAGE);
       issue(ld, (t + NS - 1) % NS);
       advance(ld, a);
     }
@@ -760,22 +715,16 @@ __device__ __forceinline__ void split_dma_tile(const SplitArgs &a, int m0, int n
             acc[i][j][r] = 0;
           }
     }
-    if (t + 1 < T && seg_last && cur.p == pmax_of(cur.d, a.s)) {
-      const double sc = ldexp(1.0, -a.bits * cur.d);
-      const bool first = cur.seg == 0 && cur.d == 2;
-      if constexpr (REG) fold_regs<M, FMW, FNW>(acc, dacc, part, sc, first);
-      else fold_partials<M, FMW, FNW, S::THREADS>(acc, dacc, plane, sc, first);
-    }
+    if (t + 1 < T && seg_last && cur.p == pmax_of(cur.d, a.s))
+      fold_partials<M, FMW, FNW, S::THREADS>(acc, dacc, plane, ldexp(1.0, -a.bits * cur.d),
+                                             cur.seg == 0 && cur.d == 2);
     advance(cur, a);
   }
 
   // Last diagonal of the last segment, then the epilogue.
   const bool only = a.s == 1 && a.seg_stages >= a.total_stages;  // a single fold in all
-  if constexpr (REG)
-    finish_regs<M, FMW, FNW>(a, acc, dacc, part, only, m0 + wm0 + 4 * g, n0 + wn0 + l16);
-  else
-    finish_tile<M, FMW, FNW, S::THREADS>(a, acc, dacc, plane, only, m0 + wm0 + 4 * g,
-                                         n0 + wn0 + l16);
+  finish_tile<M, FMW, FNW, S::THREADS>(a, acc, dacc, plane, only, m0 + wm0 + 4 * g,
+                                       n0 + wn0 + l16);
 }
 
 template <int ALGO, int WGM, int WGN, int FMW, int FNW, int NS, int SB>
@@ -924,10 +873,12 @@ __global__ __launch_bounds__(256, MINB) void split_pairs_kernel(SplitArgs a, Pai
 
   const int T = (pe - pb) * a.total_stages;
   GStep cur = first;
+  MG_LDS_POISON_STAGE(lds, 2 * STAGE);
   load(cur);
   store(0);
   __syncthreads();
   for (int t = 0; t < T; ++t) {
+    MG_LDS_POISON_STAGE(lds + ((t + 1) & 1) * STAGE, STAGE);
     GStep nxt = cur;
     advance_g(nxt);
     if (t + 1 < T) load(nxt);
@@ -1090,16 +1041,16 @@ int launch_split(int algo, const SplitArgs &a, const SplitLayout &L, hipStream_t
 }
 
 // ---------------------------------------------------------------------------
-// Batched split GEMM: many independent problems in one set of launches.
-// The preparation launches run one grid over the blocks of all problems (a
-// workgroup finds its problem by binary search over the block prefix sums);
-// the product launch runs one workgroup per 64x64 output tile of every
-// problem, longest k first, with the DMA ring's tile code and the FP64
-// partial sums in registers -- the same slices, integer products and folds
-// in the same order as the single-problem divisions, so each result is the
-// one a single call gives, bit for bit.  Per problem the workspace holds
-// only what those tiles read: E and F, and slices of A and B padded to 64
-// rows / columns and 128 k.
+// Batched split GEMM: many independent problems in one set of launches, at
+// the default slice count.  The preparation launches run one grid over the
+// blocks of all problems (a workgroup finds its problem by binary search over
+// the block prefix sums); the product launch runs one workgroup per 64x64
+// output tile of every problem, longest k first, with the all-pairs tile
+// below -- the same slices, exact integer diagonal sums and FP64 folds in the
+// same order as the single-problem divisions, so each result is the one a
+// single call gives, bit for bit.  Per problem the workspace holds only what
+// those tiles read: E and F, and slices of A and B padded to 64 rows /
+// columns and 128 k.
 struct SplitPrepDesc {
   const double *A, *B;
   int64_t lda, ldb, kp;
@@ -1115,10 +1066,7 @@ struct SplitTileRec {
   int prob, m0, n0, pad;
 };
 
-// 64x64 tile on 4 wavefronts (32x32 each), 3-stage ring of 128 bytes: three
-// workgroups per CU.
-typedef SplitDmaShape<2, 2, 2, 2, 3, 128> BatchShape;
-constexpr int kBatchWavesPerSimd = 3;
+constexpr int kBatchTile = 64;  // output tile of the batched product (64x64)
 
 // Problem that owns block b of a batched launch: the last i with first[i] <= b.
 __device__ __forceinline__ int batch_problem(const int *first, int count, int b) {
@@ -1165,31 +1113,206 @@ __global__ __launch_bounds__(256) void batched_slice_cols_kernel(const SplitPrep
                        blockIdx.x - first[i]);
 }
 
-template <int ALGO>
-__global__ __launch_bounds__(BatchShape::THREADS, kBatchWavesPerSimd) void split_batched_kernel(
-    const SplitArgs *args, const SplitTileRec *recs) {
+// All-pairs tile: one 64x64 output tile on 4 wavefronts (32x32 each).  Per
+// k stage of 64 bytes (64 INT8 / 32 BF16 values, one MFMA per 16x16 block)
+// all S slices of A and all S slices of B for the tile are in LDS at once
+// and every slice pair (p, q), p + q <= S + 1, is multiplied from them into
+// one exact INT32 accumulator set per diagonal d = p + q, held in registers
+// with the FP64 partial sums.  So each slice byte is read from memory once
+// per tile (the pair-major walk reads slice p of A once for each of its
+// S + 1 - p diagonals).  At the end of each k segment the diagonals fold in
+// increasing d, the fold order of the other divisions: P_d of a segment is
+// the same exact integer whatever order its pairs and stages are summed
+// in, so the result is the same bit for bit.
+template <int S>
+struct AllPairsShape {
+  static constexpr int THREADS = 256, BM = 64, BN = 64, SB = 64, NS = 2, FMW = 2, FNW = 2;
+  static constexpr int SLICE = 64 * SB;         // one slice's tile rows for one stage
+  static constexpr int STAGE = 2 * S * SLICE;   // S slices of A, then S of B
+  static constexpr size_t LDS_BYTES = (size_t)NS * STAGE;
+  static_assert(LDS_BYTES <= 160 * 1024, "stage ring beyond the CU's LDS");
+};
+
+// Epilogue of an all-pairs tile: the last diagonal's integer sums, folded
+// onto the partial sums, then C as in finish_tile.
+template <int FMW, int FNW>
+__device__ __forceinline__ void finish_ints(const SplitArgs &a, const i4v (&last)[FMW][FNW],
+                                            const double (&part)[FMW][FNW][4], bool only,
+                                            int row0, int col0) {
+  const double sc = ldexp(1.0, -a.bits * (a.s + 1));
+#pragma unroll
+  for (int i = 0; i < FMW; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row0 + 16 * i + r;
+      const bool row_ok = row < a.m;
+      const int er = row_ok ? a.E[row] : 0;
+      double *crow = a.C + (int64_t)(row_ok ? row : 0) * a.ldc;
+#pragma unroll
+      for (int j = 0; j < FNW; ++j) {
+        const int col = col0 + 16 * j;
+        const double fin = fma((double)last[i][j][r], sc, only ? 0.0 : part[i][j][r]);
+        if (!row_ok || col >= a.n) continue;
+        const double prod = ldexp(fin, er + a.F[col]);
+        double o = __dmul_rn(a.alpha, prod);
+        if (a.beta != 0.0) o = __dadd_rn(o, __dmul_rn(a.beta, crow[col]));
+        crow[col] = o;
+      }
+    }
+}
+
+// `a.seg_stages` and `a.total_stages` count 64-byte stages here; a.s == S.
+template <int ALGO, int S>
+__device__ __forceinline__ void split_allpairs_tile(const SplitArgs &a, int m0, int n0,
+                                                    unsigned char *lds) {
+  typedef AllPairsShape<S> SH;
+  constexpr int FMW = SH::FMW, FNW = SH::FNW, SB = SH::SB, SL = SH::SLICE;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int64_t a_slice = (int64_t)a.mp * a.kp_bytes, b_slice = (int64_t)a.np * a.kp_bytes;
+  // DMA: wavefront w loads rows 16w .. 16w+15 of every slice (1 KB per
+  // instruction); the lane supplies row 16w + lane/4, physical chunk lane%4,
+  // which holds logical chunk swz_chunk(row, lane%4).
+  const int drow = 16 * wave + (lane >> 2);
+  const int64_t asrc = (int64_t)(m0 + drow) * a.kp_bytes + swz_chunk<SB>(drow, lane & 3) * 16;
+  const int64_t bsrc = (int64_t)(n0 + drow) * a.kp_bytes + swz_chunk<SB>(drow, lane & 3) * 16;
+  auto issue = [&](int st, int stage) {
+    const int64_t koff = (int64_t)st * SB;
+    unsigned char *la = lds + stage * SH::STAGE + wave * 1024;
+#pragma unroll
+    for (int t = 0; t < S; ++t) dma16(a.As + t * a_slice + asrc + koff, la + t * SL);
+#pragma unroll
+    for (int t = 0; t < S; ++t) dma16(a.Bs + t * b_slice + bsrc + koff, la + (S + t) * SL);
+  };
+
+  i4v acc[S][FMW][FNW];  // INT32 sums of the diagonals d = 2 .. S+1 (index d - 2)
+  double part[FMW][FNW][4];
+#pragma unroll
+  for (int d = 0; d < S; ++d)
+#pragma unroll
+    for (int i = 0; i < FMW; ++i)
+#pragma unroll
+      for (int j = 0; j < FNW; ++j) acc[d][i][j] = i4v{};
+#pragma unroll
+  for (int i = 0; i < FMW; ++i)
+#pragma unroll
+    for (int j = 0; j < FNW; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) part[i][j][r] = 0.0;
+
+  const int T = a.total_stages;
+  bool first = true;  // no fold yet: the first starts from 0
+  MG_LDS_POISON_STAGE(lds, SH::NS * SH::STAGE);
+  issue(0, 0);
+  for (int t = 0; t < T; ++t) {
+    wait_vmcnt<0>();
+    __builtin_amdgcn_s_barrier();
+    if (t + 1 < T) {
+      MG_LDS_POISON_STAGE(lds + ((t + 1) & 1) * SH::STAGE, SH::STAGE);
+      issue(t + 1, (t + 1) & 1);
+    }
+    const unsigned char *As = lds + (t & 1) * SH::STAGE;
+    const unsigned char *Bs = As + S * SL;
+    i4v fb[S][FNW];
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+#pragma unroll
+      for (int j = 0; j < FNW; ++j) {
+        const int row = wn0 + 16 * j + l16;
+        fb[q][j] = *reinterpret_cast<const i4v *>(Bs + q * SL + row * SB +
+                                                  swz_chunk<SB>(row, g) * 16);
+      }
+#pragma unroll
+    for (int p = 0; p < S; ++p) {
+      i4v fa[FMW];
+#pragma unroll
+      for (int i = 0; i < FMW; ++i) {
+        const int row = wm0 + 16 * i + l16;
+        fa[i] = *reinterpret_cast<const i4v *>(As + p * SL + row * SB +
+                                               swz_chunk<SB>(row, g) * 16);
+      }
+#pragma unroll
+      for (int q = 0; q < S - p; ++q)
+#pragma unroll
+        for (int i = 0; i < FMW; ++i)
+#pragma unroll
+          for (int j = 0; j < FNW; ++j) {
+            if constexpr (ALGO == MG_SPLIT_I8) {
+              acc[p + q][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[i], fb[q][j],
+                                                                       acc[p + q][i][j], 0, 0, 0);
+            } else {  // 32 products of |x| <= 255^2: exact in FP32, then added as integers
+              const f4v c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  __builtin_bit_cast(bf8v, fa[i]), __builtin_bit_cast(bf8v, fb[q][j]), f4v{},
+                  0, 0, 0);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) acc[p + q][i][j][r] += (int)c[r];
+            }
+          }
+    }
+    // End of a k segment (but not the last): fold every diagonal, increasing d.
+    if (t + 1 < T && (t + 1) % a.seg_stages == 0) {
+#pragma unroll
+      for (int d = 0; d < S; ++d) {
+        const double sc = ldexp(1.0, -a.bits * (d + 2));
+#pragma unroll
+        for (int i = 0; i < FMW; ++i)
+#pragma unroll
+          for (int j = 0; j < FNW; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              part[i][j][r] = fma((double)acc[d][i][j][r], sc, first ? 0.0 : part[i][j][r]);
+              acc[d][i][j][r] = 0;
+            }
+        first = false;
+      }
+    }
+  }
+  // Last segment: diagonals 2 .. S, then the last one in the epilogue.
+#pragma unroll
+  for (int d = 0; d < S - 1; ++d) {
+    const double sc = ldexp(1.0, -a.bits * (d + 2));
+#pragma unroll
+    for (int i = 0; i < FMW; ++i)
+#pragma unroll
+      for (int j = 0; j < FNW; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          part[i][j][r] = fma((double)acc[d][i][j][r], sc, first ? 0.0 : part[i][j][r]);
+    first = false;
+  }
+  finish_ints<FMW, FNW>(a, acc[S - 1], part, first, m0 + wm0 + 4 * g, n0 + wn0 + l16);
+}
+
+template <int ALGO, int S>
+__global__ __launch_bounds__(256, 1) void split_allpairs_kernel(const SplitArgs *args,
+                                                                const SplitTileRec *recs) {
   extern __shared__ __align__(16) unsigned char lds[];
   const SplitTileRec r = recs[blockIdx.x];
   const SplitArgs a = args[r.prob];
-  split_dma_tile<ALGO, 2, 2, 2, 2, 3, 128, true>(a, r.m0, r.n0, nullptr, lds);
+  split_allpairs_tile<ALGO, S>(a, r.m0, r.n0, lds);
 }
+
+// Slice count of a batch (the all-pairs tile is built for the default).
+constexpr int batch_slices(int algo) { return algo == MG_SPLIT_BF16 ? 6 : 7; }
 
 template <int ALGO>
 int launch_batched_t(const SplitArgs *d_args, const SplitPrepDesc *d_desc, const int *d_first,
                      int nl, const int64_t *blocks, const SplitTileRec *d_recs, int ntiles,
-                     int slices, hipStream_t s) {
+                     hipStream_t s) {
   constexpr int ESZ = ALGO == MG_SPLIT_BF16 ? 2 : 1;
+  constexpr int S = batch_slices(ALGO);
   const int bits = split_bits(ALGO);
-  static int once = ensure_lds(split_batched_kernel<ALGO>, BatchShape::LDS_BYTES);
+  static int once = ensure_lds(split_allpairs_kernel<ALGO, S>, AllPairsShape<S>::LDS_BYTES);
   if (once != MG_OK) return once;
   hipLaunchKernelGGL(batched_fill_kernel, dim3((unsigned)blocks[0]), dim3(256), 0, s, d_desc,
                      d_first, nl);
   hipLaunchKernelGGL(batched_exp_rows_kernel<ESZ>, dim3((unsigned)blocks[1]), dim3(256), 0, s,
-                     d_desc, d_first + (nl + 1), nl, slices, bits);
+                     d_desc, d_first + (nl + 1), nl, S, bits);
   hipLaunchKernelGGL(batched_slice_cols_kernel<ESZ>, dim3((unsigned)blocks[2]), dim3(256), 0, s,
-                     d_desc, d_first + 2 * (nl + 1), nl, slices, bits);
-  hipLaunchKernelGGL(split_batched_kernel<ALGO>, dim3((unsigned)ntiles),
-                     dim3(BatchShape::THREADS), BatchShape::LDS_BYTES, s, d_args, d_recs);
+                     d_desc, d_first + 2 * (nl + 1), nl, S, bits);
+  hipLaunchKernelGGL((split_allpairs_kernel<ALGO, S>), dim3((unsigned)ntiles), dim3(256),
+                     AllPairsShape<S>::LDS_BYTES, s, d_args, d_recs);
   MG_HIP_TRY(hipGetLastError());
   return MG_OK;
 }
@@ -1577,19 +1700,19 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
-int gemm_split_batched(int algo, int slices, int64_t count, const mg_problem *probs,
-                       hipStream_t s) {
+int gemm_split_batched(int algo, int64_t count, const mg_problem *probs, hipStream_t s) {
   if (algo != MG_SPLIT_I8 && algo != MG_SPLIT_BF16) {
     set_error("not a split algorithm: %d", algo);
     return MG_ERR_INVALID_ARG;
   }
   reap_holds();
+  const int slices = batch_slices(algo);
   const int64_t seg = seg_stages_of(algo, slices);
   if (seg < 1) {
     set_error("too many slices for exact INT32 accumulation");
     return MG_ERR_INVALID_ARG;
   }
-  typedef BatchShape S;
+  constexpr int64_t TILE = kBatchTile;
   // Degenerate problems as a single call runs them; the rest are batched.
   std::vector<int64_t> live;
   for (int64_t i = 0; i < count; ++i) {
@@ -1621,8 +1744,8 @@ int gemm_split_batched(int algo, int slices, int64_t count, const mg_problem *pr
   for (int j = 0; j < nl; ++j) {
     const mg_problem &q = probs[live[(size_t)j]];
     BLayout &l = L[(size_t)j];
-    l.mr = round_up(q.m, (int64_t)S::BM);
-    l.nr = round_up(q.n, (int64_t)S::BN);
+    l.mr = round_up(q.m, TILE);
+    l.nr = round_up(q.n, TILE);
     l.kp = round_up(q.k, (int64_t)kSplitTileK);
     int64_t off = 0;
     l.e_off = off;
@@ -1669,11 +1792,11 @@ int gemm_split_batched(int algo, int slices, int64_t count, const mg_problem *pr
   for (int w = 0; w < 3; ++w) first[(size_t)w * (nl + 1) + nl] = (int)blocks[w];
   for (int j : ord) {
     const BLayout &l = L[(size_t)j];
-    for (int64_t a = 0; a < l.mr / S::BM; ++a)
-      for (int64_t b = 0; b < l.nr / S::BN; ++b)
-        recs.push_back(SplitTileRec{j, (int)(a * S::BM), (int)(b * S::BN), 0});
+    for (int64_t a = 0; a < l.mr / TILE; ++a)
+      for (int64_t b = 0; b < l.nr / TILE; ++b)
+        recs.push_back(SplitTileRec{j, (int)(a * TILE), (int)(b * TILE), 0});
   }
-  if (recs.size() * S::THREADS > (size_t)UINT32_MAX) {
+  if (recs.size() * 256 > (size_t)UINT32_MAX) {
     set_error("split batch too large for one dispatch");
     return MG_ERR_INVALID_ARG;
   }
@@ -1708,8 +1831,9 @@ int gemm_split_batched(int algo, int slices, int64_t count, const mg_problem *pr
     a.kp_bytes = l.kp * esz;
     a.s = slices;
     a.bits = bits;
-    a.total_stages = (int)(a.kp_bytes / kStageBytes);
-    a.seg_stages = (int)std::min<int64_t>(seg, a.total_stages);
+    // stage counts in the all-pairs tile's 64-byte stages
+    a.total_stages = (int)(a.kp_bytes / 64);
+    a.seg_stages = (int)std::min<int64_t>(seg * (kStageBytes / 64), a.total_stages);
     a.alpha = q.alpha;
     a.beta = q.beta;
     SplitPrepDesc &d = desc[(size_t)j];
@@ -1751,9 +1875,9 @@ int gemm_split_batched(int algo, int slices, int64_t count, const mg_problem *pr
     const auto *d_recs = reinterpret_cast<const SplitTileRec *>(dm + o_recs);
     rc = algo == MG_SPLIT_BF16
              ? launch_batched_t<MG_SPLIT_BF16>(d_args, d_desc, d_first, nl, blocks, d_recs,
-                                               (int)recs.size(), slices, s)
+                                               (int)recs.size(), s)
              : launch_batched_t<MG_SPLIT_I8>(d_args, d_desc, d_first, nl, blocks, d_recs,
-                                             (int)recs.size(), slices, s);
+                                             (int)recs.size(), s);
   }
   hipEvent_t ev = nullptr;
   if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess &&

@@ -94,6 +94,10 @@ def test_invalid_arguments(kw, code):
     assert mg.last_error() != ""
 
 
+def test_release_build_flags():
+    assert mg.build_flags() == 0
+
+
 def _fake_batch(count):
     P = mg.Problem * count
     return P(*[mg.Problem(8, 8, 8, 1.0, 1.0, 0x10000000 + 0x1000 * (3 * i), 8,

@@ -449,6 +449,34 @@ def profile_batched():
     return out
 
 
+def profile_batched_split():
+    """For counter runs: the 2000-problem FP64 batch through the batched
+    split path, 3 times with MG_SPLIT_I8, then 3 times with MG_SPLIT_BF16."""
+    import torch
+    import paper_1602_08477_amd as mg
+    import synth
+    seed = synth.config_seed(4)
+    shapes = synth.batch_shapes(seed, 2000)
+    offs = {"A": [0], "B": [0], "C": [0]}
+    for m_, n_, k_ in shapes:
+        for key, sz in (("A", m_ * k_), ("B", k_ * n_), ("C", m_ * n_)):
+            offs[key].append(offs[key][-1] + -(-int(sz) // 32) * 32)
+    flats = {key: synth.flat_uniform(seed, i, offs[key][-1], device="cuda")
+             for i, key in enumerate(("A", "B", "C"))}
+    probs = []
+    for i, (m_, n_, k_) in enumerate(shapes):
+        m_, n_, k_ = int(m_), int(n_), int(k_)
+        probs.append(mg.problem(
+            flats["A"][offs["A"][i]: offs["A"][i] + m_ * k_].view(m_, k_),
+            flats["B"][offs["B"][i]: offs["B"][i] + k_ * n_].view(k_, n_),
+            flats["C"][offs["C"][i]: offs["C"][i] + m_ * n_].view(m_, n_), 1.0, 1.0))
+    for algo in (mg.SPLIT_I8, mg.SPLIT_BF16):
+        for _ in range(3):
+            mg.gemm_batched(probs, dtype=mg.F64, algo=algo)
+        torch.cuda.synchronize()
+    return {"problems": len(probs)}
+
+
 def profile_split(n=4096):
     """For counter runs: native FP64, then split INT8 three times, then split
     BF16 once, at n = 4096 on the exponent-spread workload (alpha=1, beta=0)."""
@@ -864,8 +892,8 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--quick", action="store_true", help="headline only (for profiling)")
     ap.add_argument("--leg", choices=["sizes", "trans", "daxpy", "overhead", "split", "batched",
-                                      "serving", "profile_batched", "profile_split",
-                                      "profile_serving"],
+                                      "serving", "profile_batched", "profile_batched_split",
+                                      "profile_split", "profile_serving"],
                     default=None,
                     help="run only this secondary leg and print its record (for profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -895,6 +923,7 @@ def main():
               "batched": lambda: bench_batched(max(3, args.steps)),
               "serving": lambda: bench_serving(args.serve_seconds),
               "profile_batched": profile_batched,
+              "profile_batched_split": profile_batched_split,
               "profile_split": profile_split,
               "profile_serving": profile_serving}[args.leg]
         print(json.dumps({"leg": args.leg, "record": fn()}), flush=True)

@@ -776,7 +776,7 @@ def serve_verify(mg, synth, pools, nmax, table, seconds=1.0, rate=2000.0):
 
 def profile_serving(rate=16000.0, seconds=2.0):
     """For kernel traces: one open-loop trace of the serving mix at ``rate``
-    (default: past saturation) under a 64 GiB budget."""
+    under a 64 GiB budget."""
     import torch
     import paper_1602_08477_amd as mg
     import synth

@@ -264,7 +264,9 @@ __device__ __forceinline__ void slice_cols_body(const double *B, int64_t ldb, in
     T[kk][jj] = (gk < k && gj < n) ? B[gk * ldb + gj] : 0.0;
   }
   __syncthreads();
-  const int jj = tid >> 2, kq = tid & 3;  // column, 16-long k range (4 lanes per column)
+  // Lane -> column jj, wavefront -> 16-long k range kq: a wavefront reads 64
+  // consecutive doubles of a row of T per access (no bank conflicts).
+  const int jj = tid & 63, kq = tid >> 6;
   const int j = j0 + jj;
   // F[j] still holds INT_MIN for an all-zero (or padding) column: its scale
   // is 0, and the first k-block of the column stores that back for the
@@ -358,6 +360,12 @@ __device__ __forceinline__ void advance(Step &x, const SplitArgs &a) {
 // fold reads and writes whole contiguous rows of lanes with constant offsets.
 // Element e = (i*FNW + j)*4 + r is output row 16i + 4g + r, column 16j + l16
 // of the wave's sub-tile (g = lane/16, l16 = lane%16).
+// Blocks of a row folded / stored per memory round trip (4 FP64 values each):
+// two at most, one for tiles of 16 blocks per wave, so that the gathered
+// values fit the register budget of the largest tiles.
+template <int FMW, int FNW>
+constexpr int kFoldChunk = FMW * FNW >= 16 ? 1 : (FNW > 2 ? 2 : FNW);
+
 template <typename M, int FMW, int FNW, int THREADS>
 __device__ __forceinline__ void fold_partials(typename M::acc_t (&acc)[FMW][FNW],
                                               i4v (&dacc)[FMW][FNW], double *plane, double sc,
@@ -365,55 +373,98 @@ __device__ __forceinline__ void fold_partials(typename M::acc_t (&acc)[FMW][FNW]
   // Opaque copy of the base: keeps the compiler from hoisting all FMW*FNW*4
   // element addresses out of the k loop (64-bit each, they would not fit).
   asm volatile("" : "+v"(plane));
+  constexpr int CJ = kFoldChunk<FMW, FNW>;
 #pragma unroll
-  for (int i = 0; i < FMW; ++i) {
+  for (int i = 0; i < FMW; ++i)
 #pragma unroll
-    for (int j = 0; j < FNW; ++j)
+    for (int j0 = 0; j0 < FNW; j0 += CJ) {
+      // the chunk's loads first (one memory round trip), then the fused
+      // multiply-adds and stores
+      double part[CJ][4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        double *pp = plane + ((i * FNW + j) * 4 + r) * THREADS;
-        const int v = M::CHUNK_STAGES > 0 ? dacc[i][j][r] : (int)acc[i][j][r];
-        const double part = first ? 0.0 : *pp;
-        *pp = fma((double)v, sc, part);
-        dacc[i][j][r] = 0;
-        if (M::CHUNK_STAGES == 0) acc[i][j][r] = 0;
-      }
-    // keep one row of blocks in flight: bounds the live FP64 registers
-    __builtin_amdgcn_sched_barrier(0);
-  }
+      for (int j = 0; j < CJ; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          part[j][r] = first ? 0.0 : plane[((i * FNW + j0 + j) * 4 + r) * THREADS];
+#pragma unroll
+      for (int j = 0; j < CJ; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int v = M::CHUNK_STAGES > 0 ? dacc[i][j0 + j][r] : (int)acc[i][j0 + j][r];
+          plane[((i * FNW + j0 + j) * 4 + r) * THREADS] = fma((double)v, sc, part[j][r]);
+          dacc[i][j0 + j][r] = 0;
+          if (M::CHUNK_STAGES == 0) acc[i][j0 + j][r] = 0;
+        }
+      // one chunk in flight at a time: bounds the live FP64 registers
+      __builtin_amdgcn_sched_barrier(0);
+    }
 }
 
-// Last fold, then C = alpha * 2^(E_i + F_j) * acc + beta * C, each product and
-// the sum rounded once.  (row0, col0): this lane's first output.
+// C = alpha * 2^(E_i + F_j) * fin + beta * C for one block of this lane's
+// outputs (rows rowb .. rowb+3, columns col0 + 16j), each product and the sum
+// rounded once.  Every operand (E, F, and C when beta != 0) is loaded first,
+// from addresses clamped into the matrix, so the loads are in flight
+// together (one memory round trip, not one per output); values of rows or
+// columns outside the matrix are computed and not stored.
+template <int FNW>
+__device__ __forceinline__ void store_block(const SplitArgs &a, const double (&fin)[4][FNW],
+                                            int rowb, int col0) {
+  int er[4], fc[FNW], cc[FNW];
+  int64_t roff[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = min(rowb + r, a.m - 1);
+    er[r] = a.E[row];
+    roff[r] = (int64_t)row * a.ldc;
+  }
+#pragma unroll
+  for (int j = 0; j < FNW; ++j) {
+    cc[j] = min(col0 + 16 * j, a.n - 1);
+    fc[j] = a.F[cc[j]];
+  }
+  const bool with_c = a.beta != 0.0;
+  double cv[4][FNW];
+  if (with_c) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int j = 0; j < FNW; ++j) cv[r][j] = a.C[roff[r] + cc[j]];
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int j = 0; j < FNW; ++j) {
+      const double prod = ldexp(fin[r][j], er[r] + fc[j]);
+      double o = __dmul_rn(a.alpha, prod);
+      if (with_c) o = __dadd_rn(o, __dmul_rn(a.beta, cv[r][j]));
+      if (rowb + r < a.m && col0 + 16 * j < a.n) a.C[roff[r] + cc[j]] = o;
+    }
+}
+
+// Last fold, then the epilogue.  (row0, col0): this lane's first output.
 template <typename M, int FMW, int FNW, int THREADS>
 __device__ __forceinline__ void finish_tile(const SplitArgs &a, typename M::acc_t (&acc)[FMW][FNW],
                                             i4v (&dacc)[FMW][FNW], const double *plane,
                                             bool only, int row0, int col0) {
   const double sc = ldexp(1.0, -a.bits * (a.s + 1));
   asm volatile("" : "+v"(plane));
+  constexpr int CJ = kFoldChunk<FMW, FNW>;
 #pragma unroll
-  for (int i = 0; i < FMW; ++i) {
+  for (int i = 0; i < FMW; ++i)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = row0 + 16 * i + r;
-      const bool row_ok = row < a.m;
-      const int er = row_ok ? a.E[row] : 0;
-      double *crow = a.C + (int64_t)(row_ok ? row : 0) * a.ldc;
+    for (int j0 = 0; j0 < FNW; j0 += CJ) {
+      double fin[4][CJ];
 #pragma unroll
-      for (int j = 0; j < FNW; ++j) {
-        const int col = col0 + 16 * j;
-        const int v = M::CHUNK_STAGES > 0 ? dacc[i][j][r] : (int)acc[i][j][r];
-        const double part = only ? 0.0 : plane[((i * FNW + j) * 4 + r) * THREADS];
-        const double fin = fma((double)v, sc, part);
-        if (!row_ok || col >= a.n) continue;
-        const double prod = ldexp(fin, er + a.F[col]);
-        double o = __dmul_rn(a.alpha, prod);
-        if (a.beta != 0.0) o = __dadd_rn(o, __dmul_rn(a.beta, crow[col]));
-        crow[col] = o;
-      }
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < CJ; ++j) {
+          const int v = M::CHUNK_STAGES > 0 ? dacc[i][j0 + j][r] : (int)acc[i][j0 + j][r];
+          const double part = only ? 0.0 : plane[((i * FNW + j0 + j) * 4 + r) * THREADS];
+          fin[r][j] = fma((double)v, sc, part);
+        }
+      store_block<CJ>(a, fin, row0 + 16 * i, col0 + 16 * j0);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    __builtin_amdgcn_sched_barrier(0);
-  }
 }
 
 // Work divisions of the product kernel: WGM x WGN wavefronts, each owning
@@ -1143,24 +1194,15 @@ __device__ __forceinline__ void finish_ints(const SplitArgs &a, const i4v (&last
                                             int row0, int col0) {
   const double sc = ldexp(1.0, -a.bits * (a.s + 1));
 #pragma unroll
-  for (int i = 0; i < FMW; ++i)
+  for (int i = 0; i < FMW; ++i) {
+    double fin[4][FNW];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = row0 + 16 * i + r;
-      const bool row_ok = row < a.m;
-      const int er = row_ok ? a.E[row] : 0;
-      double *crow = a.C + (int64_t)(row_ok ? row : 0) * a.ldc;
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int j = 0; j < FNW; ++j) {
-        const int col = col0 + 16 * j;
-        const double fin = fma((double)last[i][j][r], sc, only ? 0.0 : part[i][j][r]);
-        if (!row_ok || col >= a.n) continue;
-        const double prod = ldexp(fin, er + a.F[col]);
-        double o = __dmul_rn(a.alpha, prod);
-        if (a.beta != 0.0) o = __dadd_rn(o, __dmul_rn(a.beta, crow[col]));
-        crow[col] = o;
-      }
-    }
+      for (int j = 0; j < FNW; ++j)
+        fin[r][j] = fma((double)last[i][j][r], sc, only ? 0.0 : part[i][j][r]);
+    store_block<FNW>(a, fin, row0 + 16 * i, col0);
+  }
 }
 
 // `a.seg_stages` and `a.total_stages` count 64-byte stages here; a.s == S.

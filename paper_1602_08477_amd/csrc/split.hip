@@ -252,6 +252,10 @@ template <int ESZ>
 __device__ __forceinline__ void slice_cols_body(const double *B, int64_t ldb, int k, int n,
                                                 int np, int64_t kp, int *F, int s, int bits,
                                                 unsigned char *out, int block) {
+  // (Measured alternatives: one wavefront per 16-long k range reading 64
+  // consecutive columns has no LDS bank conflicts but writes 16-byte pieces
+  // of 64 columns, 25 % slower in the 2000-problem batch; rotating T's
+  // columns per 16-row block left the conflict count unchanged.)
   __shared__ double T[64][65];
   const int64_t kblocks = kp / 64;
   const int j0 = (int)(block / kblocks) * 64;
@@ -264,9 +268,9 @@ __device__ __forceinline__ void slice_cols_body(const double *B, int64_t ldb, in
     T[kk][jj] = (gk < k && gj < n) ? B[gk * ldb + gj] : 0.0;
   }
   __syncthreads();
-  // Lane -> column jj, wavefront -> 16-long k range kq: a wavefront reads 64
-  // consecutive doubles of a row of T per access (no bank conflicts).
-  const int jj = tid & 63, kq = tid >> 6;
+  // column jj, 16-long k range kq: the 4 lanes of a column write its 64
+  // contiguous bytes of each slice
+  const int jj = tid >> 2, kq = tid & 3;
   const int j = j0 + jj;
   // F[j] still holds INT_MIN for an all-zero (or padding) column: its scale
   // is 0, and the first k-block of the column stores that back for the
@@ -1177,9 +1181,12 @@ __global__ __launch_bounds__(256) void batched_slice_cols_kernel(const SplitPrep
 // increasing d, the fold order of the other divisions: P_d of a segment is
 // the same exact integer whatever order its pairs and stages are summed
 // in, so the result is the same bit for bit.
-template <int S>
+// NS = 2: a 2-stage ring, one workgroup per CU; NS = 1: one stage, refilled
+// after every workgroup has read it, two workgroups per CU (each one's loads
+// and per-tile work overlap the other's products).
+template <int S, int NS_ = 2>
 struct AllPairsShape {
-  static constexpr int THREADS = 256, BM = 64, BN = 64, SB = 64, NS = 2, FMW = 2, FNW = 2;
+  static constexpr int THREADS = 256, BM = 64, BN = 64, SB = 64, NS = NS_, FMW = 2, FNW = 2;
   static constexpr int SLICE = 64 * SB;         // one slice's tile rows for one stage
   static constexpr int STAGE = 2 * S * SLICE;   // S slices of A, then S of B
   static constexpr size_t LDS_BYTES = (size_t)NS * STAGE;
@@ -1206,10 +1213,10 @@ __device__ __forceinline__ void finish_ints(const SplitArgs &a, const i4v (&last
 }
 
 // `a.seg_stages` and `a.total_stages` count 64-byte stages here; a.s == S.
-template <int ALGO, int S>
+template <int ALGO, int S, int NS>
 __device__ __forceinline__ void split_allpairs_tile(const SplitArgs &a, int m0, int n0,
                                                     unsigned char *lds) {
-  typedef AllPairsShape<S> SH;
+  typedef AllPairsShape<S, NS> SH;
   constexpr int FMW = SH::FMW, FNW = SH::FNW, SB = SH::SB, SL = SH::SLICE;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
@@ -1247,16 +1254,24 @@ __device__ __forceinline__ void split_allpairs_tile(const SplitArgs &a, int m0, 
 
   const int T = a.total_stages;
   bool first = true;  // no fold yet: the first starts from 0
-  MG_LDS_POISON_STAGE(lds, SH::NS * SH::STAGE);
-  issue(0, 0);
+  if constexpr (NS == 2) {
+    MG_LDS_POISON_STAGE(lds, SH::NS * SH::STAGE);
+    issue(0, 0);
+  }
   for (int t = 0; t < T; ++t) {
+    if constexpr (NS == 1) {
+      MG_LDS_POISON_STAGE(lds, SH::STAGE);
+      issue(t, 0);
+    }
     wait_vmcnt<0>();
     __builtin_amdgcn_s_barrier();
-    if (t + 1 < T) {
-      MG_LDS_POISON_STAGE(lds + ((t + 1) & 1) * SH::STAGE, SH::STAGE);
-      issue(t + 1, (t + 1) & 1);
+    if constexpr (NS == 2) {
+      if (t + 1 < T) {
+        MG_LDS_POISON_STAGE(lds + ((t + 1) & 1) * SH::STAGE, SH::STAGE);
+        issue(t + 1, (t + 1) & 1);
+      }
     }
-    const unsigned char *As = lds + (t & 1) * SH::STAGE;
+    const unsigned char *As = lds + (NS == 2 ? (t & 1) : 0) * SH::STAGE;
     const unsigned char *Bs = As + S * SL;
     i4v fb[S][FNW];
 #pragma unroll
@@ -1294,6 +1309,8 @@ __device__ __forceinline__ void split_allpairs_tile(const SplitArgs &a, int m0, 
             }
           }
     }
+    // one stage: every wavefront has read it before the next load overwrites it
+    if constexpr (NS == 1) __builtin_amdgcn_s_barrier();
     // End of a k segment (but not the last): fold every diagonal, increasing d.
     if (t + 1 < T && (t + 1) % a.seg_stages == 0) {
 #pragma unroll
@@ -1328,14 +1345,20 @@ __device__ __forceinline__ void split_allpairs_tile(const SplitArgs &a, int m0, 
   finish_ints<FMW, FNW>(a, acc[S - 1], part, first, m0 + wm0 + 4 * g, n0 + wn0 + l16);
 }
 
-template <int ALGO, int S>
-__global__ __launch_bounds__(256, 1) void split_allpairs_kernel(const SplitArgs *args,
-                                                                const SplitTileRec *recs) {
+template <int ALGO, int S, int NS>
+__global__ __launch_bounds__(256, NS == 1 ? 2 : 1) void split_allpairs_kernel(
+    const SplitArgs *args, const SplitTileRec *recs) {
   extern __shared__ __align__(16) unsigned char lds[];
   const SplitTileRec r = recs[blockIdx.x];
   const SplitArgs a = args[r.prob];
-  split_allpairs_tile<ALGO, S>(a, r.m0, r.n0, lds);
+  split_allpairs_tile<ALGO, S, NS>(a, r.m0, r.n0, lds);
 }
+
+// Stages of the batched product tile: one, with two workgroups per CU
+// (measured against the 2-stage ring at one per CU, 2000-problem batch:
+// INT8 1.92 against 2.05 ms, BF16 2.53 against 3.01 ms; uniform 1024^3
+// batches 0.70 against 0.91 ms).
+constexpr int kAllPairsNS = 1;
 
 // Slice count of a batch (the all-pairs tile is built for the default).
 constexpr int batch_slices(int algo) { return algo == MG_SPLIT_BF16 ? 6 : 7; }
@@ -1347,7 +1370,8 @@ int launch_batched_t(const SplitArgs *d_args, const SplitPrepDesc *d_desc, const
   constexpr int ESZ = ALGO == MG_SPLIT_BF16 ? 2 : 1;
   constexpr int S = batch_slices(ALGO);
   const int bits = split_bits(ALGO);
-  static int once = ensure_lds(split_allpairs_kernel<ALGO, S>, AllPairsShape<S>::LDS_BYTES);
+  typedef AllPairsShape<S, kAllPairsNS> SH;
+  static int once = ensure_lds(split_allpairs_kernel<ALGO, S, kAllPairsNS>, SH::LDS_BYTES);
   if (once != MG_OK) return once;
   hipLaunchKernelGGL(batched_fill_kernel, dim3((unsigned)blocks[0]), dim3(256), 0, s, d_desc,
                      d_first, nl);
@@ -1355,8 +1379,8 @@ int launch_batched_t(const SplitArgs *d_args, const SplitPrepDesc *d_desc, const
                      d_desc, d_first + (nl + 1), nl, S, bits);
   hipLaunchKernelGGL(batched_slice_cols_kernel<ESZ>, dim3((unsigned)blocks[2]), dim3(256), 0, s,
                      d_desc, d_first + 2 * (nl + 1), nl, S, bits);
-  hipLaunchKernelGGL((split_allpairs_kernel<ALGO, S>), dim3((unsigned)ntiles), dim3(256),
-                     AllPairsShape<S>::LDS_BYTES, s, d_args, d_recs);
+  hipLaunchKernelGGL((split_allpairs_kernel<ALGO, S, kAllPairsNS>), dim3((unsigned)ntiles),
+                     dim3(256), SH::LDS_BYTES, s, d_args, d_recs);
   MG_HIP_TRY(hipGetLastError());
   return MG_OK;
 }

@@ -322,9 +322,17 @@ def problem(A, B, C, alpha=1.0, beta=0.0) -> Problem:
     return Problem(m, n, k, alpha, beta, pa, lda, pb, ldb, pc, ldc)
 
 
+def problems_array(probs):
+    """A ctypes array of Problem descriptors, built once: the batched calls
+    take it in place of a list and pass it through without copying (for a
+    batch launched many times, this takes the per-call marshalling out)."""
+    return (Problem * max(1, len(probs)))(*probs), len(probs)
+
+
 def _problems(probs):
-    arr = (Problem * max(1, len(probs)))(*probs)
-    return arr, len(probs)
+    if isinstance(probs, tuple) and len(probs) == 2 and isinstance(probs[0], ctypes.Array):
+        return probs  # from problems_array
+    return problems_array(probs)
 
 
 def grouped_class_info(cls: int) -> tuple:

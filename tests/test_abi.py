@@ -94,6 +94,15 @@ def test_invalid_arguments(kw, code):
     assert mg.last_error() != ""
 
 
+def test_problems_array_passes_through():
+    probs = [mg.Problem(8, 8, 8, 1.0, 0.0, 0x1000 * i, 8, 0x1000 * i + 512, 8,
+                        0x1000 * i + 1024, 8) for i in range(5)]
+    arr = mg.problems_array(probs)
+    assert mg._problems(arr) is arr and arr[1] == 5
+    built, n = mg._problems(probs)
+    assert n == 5 and [built[i].A for i in range(5)] == [p.A for p in probs]
+
+
 def test_release_build_flags():
     assert mg.build_flags() == 0
 

@@ -1350,6 +1350,7 @@ __global__ __launch_bounds__(256, NS == 1 ? 2 : 1) void split_allpairs_kernel(
     const SplitArgs *args, const SplitTileRec *recs) {
   extern __shared__ __align__(16) unsigned char lds[];
   const SplitTileRec r = recs[blockIdx.x];
+  if (r.prob < 0) return;  // padding of an XCD's share of the list
   const SplitArgs a = args[r.prob];
   split_allpairs_tile<ALGO, S, NS>(a, r.m0, r.n0, lds);
 }
@@ -1858,11 +1859,45 @@ int gemm_split_batched(int algo, int64_t count, const mg_problem *probs, hipStre
     }
   }
   for (int w = 0; w < 3; ++w) first[(size_t)w * (nl + 1) + nl] = (int)blocks[w];
-  for (int j : ord) {
-    const BLayout &l = L[(size_t)j];
-    for (int64_t a = 0; a < l.mr / TILE; ++a)
-      for (int64_t b = 0; b < l.nr / TILE; ++b)
-        recs.push_back(SplitTileRec{j, (int)(a * TILE), (int)(b * TILE), 0});
+  // Problems go to XCDs whole (the dispatcher places workgroup b on XCD
+  // b mod 8), so the tiles that share a problem's slices share one L2:
+  // problems, longest k first, each to the XCD with the least work so far.
+  // A problem of 16 tiles or more is cut into 8 runs of consecutive tiles
+  // (row-major, so a run shares rows of A), one per XCD, least loaded first.
+  // The XCD lists are then interleaved, shorter ones padded with no-op
+  // records.
+  {
+    constexpr int64_t kSpreadTiles = 16;
+    std::vector<std::vector<SplitTileRec>> xl(kNumXcd);
+    std::vector<double> load(kNumXcd, 0.0);
+    std::vector<int> byload(kNumXcd);
+    for (int j : ord) {
+      const BLayout &l = L[(size_t)j];
+      const int64_t tm = l.mr / TILE, tn = l.nr / TILE, nt = tm * tn;
+      auto rec = [&](int64_t t) {
+        return SplitTileRec{j, (int)((t / tn) * TILE), (int)((t % tn) * TILE), 0};
+      };
+      if (nt < kSpreadTiles) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[(size_t)x] += (double)nt * (double)l.kp;
+        for (int64_t t = 0; t < nt; ++t) xl[(size_t)x].push_back(rec(t));
+        continue;
+      }
+      std::iota(byload.begin(), byload.end(), 0);
+      std::stable_sort(byload.begin(), byload.end(),
+                       [&](int p, int q) { return load[(size_t)p] < load[(size_t)q]; });
+      for (int c = 0; c < kNumXcd; ++c) {
+        const int64_t t0 = nt * c / kNumXcd, t1 = nt * (c + 1) / kNumXcd;
+        const int x = byload[(size_t)c];
+        load[(size_t)x] += (double)(t1 - t0) * (double)l.kp;
+        for (int64_t t = t0; t < t1; ++t) xl[(size_t)x].push_back(rec(t));
+      }
+    }
+    size_t len = 0;
+    for (const auto &v : xl) len = std::max(len, v.size());
+    recs.assign(len * kNumXcd, SplitTileRec{-1, 0, 0, 0});
+    for (int x = 0; x < kNumXcd; ++x)
+      for (size_t i = 0; i < xl[(size_t)x].size(); ++i) recs[i * kNumXcd + (size_t)x] = xl[(size_t)x][i];
   }
   if (recs.size() * 256 > (size_t)UINT32_MAX) {
     set_error("split batch too large for one dispatch");

@@ -203,9 +203,15 @@ int mg_gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double 
  * slice pairs are cut into groups, each workgroup sums one group's pairs for
  * one 128x128 tile and writes exact INT32 partial diagonal sums, and a second
  * kernel adds them and folds them into FP64 as the other divisions do
- * (MG_ERR_INVALID_ARG on larger shapes).  mg_gemm_split picks by size;
- * mg_gemm_split_cfg takes cfg explicitly (-1 = pick).  MG_ERR_INVALID_ARG for
- * an unknown cfg. */
+ * (MG_ERR_INVALID_ARG on larger shapes); 16: all-pairs, default slice count
+ * only (MG_ERR_INVALID_ARG otherwise): a 64x64 tile on 4 wavefronts holds
+ * every slice of its rows of A and columns of B for one 64-byte k stage in
+ * LDS and forms all slice pairs from it, one exact INT32 sum per diagonal and
+ * the FP64 partial sums in registers, two workgroups per CU (needs no
+ * partial-sum region: p_off bytes of workspace suffice).  mg_gemm_split and
+ * mg_gemm pick by size (16 up to n = 2048 INT8 / 1024 BF16 at the default
+ * slice count); mg_gemm_split_cfg takes cfg explicitly (-1 = pick).
+ * MG_ERR_INVALID_ARG for an unknown cfg. */
 int mg_split_num_cfgs(void);
 int mg_gemm_split_cfg(int algo, int slices, int cfg, int64_t m, int64_t n, int64_t k,
                       double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,

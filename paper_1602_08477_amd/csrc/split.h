@@ -33,11 +33,13 @@ int split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, const d
 
 // Work divisions of the product kernel; cfg < 0 picks by size.
 int split_num_cfgs();
-// `latency`: one call on an otherwise idle device (the pair-parallel division
-// below two 128x128 tiles per CU); false: a device shared with other work
+// `latency`: one call on an otherwise idle device (the all-pairs 64x64 tile at
+// the default slice count up to n = 2048 INT8 / 1024 BF16, the pair-parallel
+// division for other slice counts below one 128x128 tile per CU); false: a
+// device shared with other work
 // (fused divisions only, the most throughput per FLOP).  Both give the same
 // bits.
-int split_pick_cfg(int algo, int64_t mp, int64_t np, bool latency);
+int split_pick_cfg(int algo, int slices, int64_t mp, int64_t np, bool latency);
 // Workspace bytes the division `cfg` needs (<= the layout's total), and
 // those of the division split_pick_cfg would pick.
 int64_t split_ws_needed(const SplitLayout &L, int cfg);

@@ -1355,6 +1355,16 @@ __global__ __launch_bounds__(256, NS == 1 ? 2 : 1) void split_allpairs_kernel(
   split_allpairs_tile<ALGO, S, NS>(a, r.m0, r.n0, lds);
 }
 
+// The all-pairs tile over one problem's 64x64 tiles (work division 16).
+template <int ALGO, int S, int NS>
+__global__ __launch_bounds__(256, NS == 1 ? 2 : 1) void split_allpairs_grid_kernel(
+    SplitArgs a, int tiles_m, int tiles_n) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  int tm, tn;
+  grouped_tile(xcd_remap(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, tm, tn);
+  split_allpairs_tile<ALGO, S, NS>(a, tm * 64, tn * 64, lds);
+}
+
 // Stages of the batched product tile: one, with two workgroups per CU
 // (measured against the 2-stage ring at one per CU, 2000-problem batch:
 // INT8 1.92 against 2.05 ms, BF16 2.53 against 3.01 ms; uniform 1024^3
@@ -1382,6 +1392,30 @@ int launch_batched_t(const SplitArgs *d_args, const SplitPrepDesc *d_desc, const
                      d_desc, d_first + 2 * (nl + 1), nl, S, bits);
   hipLaunchKernelGGL((split_allpairs_kernel<ALGO, S, kAllPairsNS>), dim3((unsigned)ntiles),
                      dim3(256), SH::LDS_BYTES, s, d_args, d_recs);
+  MG_HIP_TRY(hipGetLastError());
+  return MG_OK;
+}
+
+// Work division 16: the all-pairs tile on the single-problem workspace (its
+// slice pitches mp, np; the partial-sum region unused); only the tiles that
+// hold outputs run.  `a` counts 128-byte stages.
+template <int ALGO>
+int launch_allpairs_t(const SplitArgs &a128, hipStream_t s) {
+  constexpr int S = batch_slices(ALGO);
+  typedef AllPairsShape<S, kAllPairsNS> SH;
+  if (a128.s != S) {
+    set_error("split work division 16 takes the default slice count (%d)", S);
+    return MG_ERR_INVALID_ARG;
+  }
+  auto kern = split_allpairs_grid_kernel<ALGO, S, kAllPairsNS>;
+  static int once = ensure_lds(kern, SH::LDS_BYTES);
+  if (once != MG_OK) return once;
+  SplitArgs a = a128;  // stage counts in 64-byte stages
+  a.total_stages = a128.total_stages * (kStageBytes / SH::SB);
+  a.seg_stages = a128.seg_stages * (kStageBytes / SH::SB);
+  const int tiles_m = (int)ceil_div(a.m, SH::BM), tiles_n = (int)ceil_div(a.n, SH::BN);
+  hipLaunchKernelGGL(kern, dim3((unsigned)(tiles_m * tiles_n)), dim3(SH::THREADS), SH::LDS_BYTES,
+                     s, a, tiles_m, tiles_n);
   MG_HIP_TRY(hipGetLastError());
   return MG_OK;
 }
@@ -1533,13 +1567,22 @@ int split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, const d
   return MG_OK;
 }
 
-int split_num_cfgs() { return 16; }
+int split_num_cfgs() { return 17; }
 
 // Product-kernel work division (measured on MI355X at n = 4096): the 256x256
 // direct-to-LDS tile once every CU gets one, then the 128x256 one, else the
 // register-staged 128x128 tile.
-int split_pick_cfg(int algo, int64_t mp, int64_t np, bool latency) {
-  // Below one 128x128 tile per CU, for one call's latency, the pair-parallel
+int split_pick_cfg(int algo, int slices, int64_t mp, int64_t np, bool latency) {
+  // For one call's latency, at the default slice count, the all-pairs 64x64
+  // tile (16) up to n = 2048 (INT8) / 1024 (BF16): whole INT8 call n = 256 /
+  // 512 / 1024 / 2048: 50 / 57 / 90 / 304 us against 76 / 100 / 139 / 428
+  // for the pair-parallel division and the 128x128 ring; at n = 4096 2.17
+  // against 1.89 ms for the 256x256 ring.  BF16 n = 1024: 163 against 223 us;
+  // n = 2048: 632 against 554.
+  if (latency && slices == split_default_slices(algo) &&
+      mp * np <= (algo == MG_SPLIT_BF16 ? (int64_t)1024 * 1024 : (int64_t)2048 * 2048))
+    return 16;
+  // Other slice counts below one 128x128 tile per CU: the pair-parallel
   // division (15): the fused divisions would give too few workgroups, each
   // walking all the slice pairs as one chain of dependent loads.  When the
   // device is shared (the server's batches) the fused divisions give more
@@ -1596,7 +1639,7 @@ int split_multiply(int algo, int slices, int64_t m, int64_t n, int64_t k, double
   a.seg_stages = (int)std::min<int64_t>(seg_stages, a.total_stages);
   a.alpha = alpha;
   a.beta = beta;
-  if (cfg < 0) cfg = split_pick_cfg(algo, L.mp, L.np, true);
+  if (cfg < 0) cfg = split_pick_cfg(algo, slices, L.mp, L.np, true);
   switch (cfg) {
     case 0: return launch_split<2, 2, 4, 4>(algo, a, L, s);          // 128x128, 4 waves, registers
     case 1: return launch_split_dma<2, 2, 4, 4, 4>(algo, a, L, s);   // 128x128, 4 waves, ring of 4
@@ -1613,6 +1656,9 @@ int split_multiply(int algo, int slices, int64_t m, int64_t n, int64_t k, double
     case 12: return launch_split_dma<2, 4, 4, 2, 2, 128>(algo, a, L, s);  // 128x128, 8 waves, 2 x 128 B
     case 13: return launch_split_dma<2, 2, 4, 4, 2, 128>(algo, a, L, s);  // 128x128, 4 waves, 2 x 128 B
     case 14: return launch_split_dma<2, 4, 4, 2, 3, 128>(algo, a, L, s);  // 128x128, 8 waves, 3 x 128 B
+    case 16:  // all-pairs 64x64 tile, one LDS stage, two workgroups per CU
+      return algo == MG_SPLIT_BF16 ? launch_allpairs_t<MG_SPLIT_BF16>(a, s)
+                                   : launch_allpairs_t<MG_SPLIT_I8>(a, s);
     case 15: {  // pair-parallel: groups of slice pairs x 128x128 tiles, then the fold
       if (!pairs_eligible(L.mp, L.np)) {
         set_error("split work division 15 serves shapes with fewer than %lld tiles of 128x128",
@@ -1638,7 +1684,7 @@ int gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double alp
   if (rc != MG_OK) return rc;
   if (alpha == 0.0 || k == 0)  // C <- beta*C: A and B are not read
     return gemm_native(MG_F64, 0, m, n, 0, 0.0, nullptr, 1, nullptr, 1, beta, C, ldc, s);
-  const int use = cfg < 0 ? split_pick_cfg(algo, L.mp, L.np, true) : cfg;
+  const int use = cfg < 0 ? split_pick_cfg(algo, slices, L.mp, L.np, true) : cfg;
   if (ws == nullptr || ws_bytes < split_ws_needed(L, use)) {
     set_error("split workspace too small: need %lld bytes", (long long)split_ws_needed(L, use));
     return MG_ERR_INVALID_ARG;
@@ -1649,6 +1695,7 @@ int gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double alp
 }
 
 int64_t split_ws_needed(const SplitLayout &L, int cfg) {
+  if (cfg == 16) return L.p_off;  // partial sums stay in registers
   return cfg == 15 ? L.total : round_up(L.p_off + 8 * L.mp * L.np, 256);
 }
 
@@ -1656,7 +1703,7 @@ int64_t split_workspace_bytes(int algo, int slices, int64_t m, int64_t n, int64_
                               bool latency) {
   SplitLayout L;
   if (split_layout(algo, slices, m, n, k, &L) != MG_OK) return -1;
-  return split_ws_needed(L, split_pick_cfg(algo, L.mp, L.np, latency));
+  return split_ws_needed(L, split_pick_cfg(algo, slices, L.mp, L.np, latency));
 }
 
 namespace {
@@ -1734,7 +1781,7 @@ int gemm_split_pooled(int algo, int slices, int64_t m, int64_t n, int64_t k, dou
   if (rc != MG_OK) return rc;
   if (alpha == 0.0 || k == 0)
     return gemm_split(algo, slices, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, 0, s);
-  const int cfg = split_pick_cfg(algo, L.mp, L.np, latency);
+  const int cfg = split_pick_cfg(algo, slices, L.mp, L.np, latency);
   const int64_t bytes = split_ws_needed(L, cfg);
   void *ws = nullptr;
   rc = pool_alloc(&ws, bytes, s);

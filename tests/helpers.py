@@ -20,7 +20,7 @@ DMA_CFGS = (14, 15, 16, 17, 18, 19, 20, 21, 22, 23, 24, 26, 27, 28, 29)
 # (not the register-staged tiles' order, so not bit-identical to them).
 KGROUP_CFGS = (26, 27, 28, 29)
 # Split product-kernel work divisions (mg_split_num_cfgs), all covered likewise.
-SPLIT_CFGS = 16
+SPLIT_CFGS = 17
 
 U64 = 2.0 ** -53  # unit roundoff of FP64
 U32 = 2.0 ** -24

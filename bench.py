@@ -818,7 +818,7 @@ def bench_serving(seconds, rate=2000.0):
                                      1 << 30, table)
     out["saturation"] = [serve_trace(mg, synth, synth.config_seed(5, 2 + i), r,
                                      min(seconds, 3.0), *args, 64 << 30, table)
-                         for i, r in enumerate((8000.0, 16000.0, 32000.0))]
+                         for i, r in enumerate((8000.0, 16000.0, 32000.0, 64000.0))]
     del arena
     torch.cuda.empty_cache()
     out["verify"] = serve_verify(mg, synth, pools, nmax, table)

@@ -44,6 +44,7 @@ struct Lane {
   size_t d_cap = 0;
   void *h_buf = nullptr;  // pinned staging
   size_t h_cap = 0;
+  SplitBatchBuffers sb[2];  // split batches' workspace and staging (INT8, BF16)
   std::vector<Req *> batch;
   int64_t sim_done_ns = 0;  // host simulation: when the batch "completes"
   bool busy = false;      // owns a batch (being launched or in flight)
@@ -190,7 +191,10 @@ void launch_batch(Server *S, Lane &L, int64_t batch_id) {
     for (Req *q : L.batch)
       if (q->r.algo == algo) ps.push_back(q->r.p);
     if (ps.empty()) continue;
-    const int r2 = gemm_split_batched(algo, (int64_t)ps.size(), ps.data(), L.s);
+    // the lane's own buffers: its previous batch has completed, so they are
+    // free, and the batch allocates nothing
+    const int r2 = gemm_split_batched(algo, (int64_t)ps.size(), ps.data(), L.s,
+                                      &L.sb[algo == MG_SPLIT_BF16 ? 1 : 0]);
     if (r2 != MG_OK)
       for (Req *q : L.batch)
         if (q->r.algo == algo) q->res.status = r2;
@@ -281,6 +285,7 @@ void destroy_lanes(Server *S) {
     if (L.s) (void)hipStreamDestroy(L.s);
     if (L.d_buf) (void)hipFree(L.d_buf);
     if (L.h_buf) (void)hipHostFree(L.h_buf);
+    for (SplitBatchBuffers &b : L.sb) b.release();
   }
 }
 

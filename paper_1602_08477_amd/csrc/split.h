@@ -66,11 +66,25 @@ int gemm_split_pooled(int algo, int slices, int64_t m, int64_t n, int64_t k, dou
 int workspace_pool(hipMemPool_t *out);
 int release_workspace_pools();
 
+// Device workspace and pinned host staging that a caller who runs batches one
+// after another on one stream keeps between calls (the server's lanes), so a
+// batch allocates and frees nothing; grown on demand, never shrunk.
+struct SplitBatchBuffers {
+  void *d = nullptr, *h = nullptr;
+  size_t d_cap = 0, h_cap = 0;
+  // Grows the buffers (hipMalloc / hipHostMalloc); the caller guarantees that
+  // no work still uses them.
+  int reserve(size_t dev_bytes, size_t host_bytes);
+  void release();
+};
+
 // Many independent FP64 problems (validated descriptors) in one set of
 // launches, at the default slice count: per-problem workspaces in one
-// allocation from the workspace pool, batched preparation, one product
-// launch over the 64x64 output tiles of all problems.  Each result equals a
-// single call's bit for bit.
-int gemm_split_batched(int algo, int64_t count, const mg_problem *probs, hipStream_t s);
+// allocation (from the workspace pool, freed on `s` after the batch; or in
+// `buf`, whose previous contents must no longer be in use), batched
+// preparation, one product launch over the 64x64 output tiles of all
+// problems.  Each result equals a single call's bit for bit.
+int gemm_split_batched(int algo, int64_t count, const mg_problem *probs, hipStream_t s,
+                       SplitBatchBuffers *buf = nullptr);
 
 }  // namespace mg

@@ -1816,7 +1816,37 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
-int gemm_split_batched(int algo, int64_t count, const mg_problem *probs, hipStream_t s) {
+int SplitBatchBuffers::reserve(size_t dev_bytes, size_t host_bytes) {
+  // the caller guarantees that no launch still uses the old buffers
+  // (doubling growth: a few reallocations over a server's life)
+  if (dev_bytes > d_cap) {
+    const size_t cap = std::max(dev_bytes, 2 * d_cap);
+    if (d) (void)hipFree(d);
+    d = nullptr;
+    d_cap = 0;
+    MG_HIP_TRY(hipMalloc(&d, cap));
+    d_cap = cap;
+  }
+  if (host_bytes > h_cap) {
+    const size_t cap = std::max({host_bytes, 2 * h_cap, (size_t)1 << 20});
+    if (h) (void)hipHostFree(h);
+    h = nullptr;
+    h_cap = 0;
+    MG_HIP_TRY(hipHostMalloc(&h, cap, hipHostMallocDefault));
+    h_cap = cap;
+  }
+  return MG_OK;
+}
+
+void SplitBatchBuffers::release() {
+  if (d) (void)hipFree(d);
+  if (h) (void)hipHostFree(h);
+  d = h = nullptr;
+  d_cap = h_cap = 0;
+}
+
+int gemm_split_batched(int algo, int64_t count, const mg_problem *probs, hipStream_t s,
+                       SplitBatchBuffers *buf) {
   if (algo != MG_SPLIT_I8 && algo != MG_SPLIT_BF16) {
     set_error("not a split algorithm: %d", algo);
     return MG_ERR_INVALID_ARG;
@@ -1956,9 +1986,17 @@ int gemm_split_batched(int algo, int64_t count, const mg_problem *probs, hipStre
   const size_t o_recs = align256(o_first + first.size() * sizeof(int));
   const size_t meta = align256(o_recs + recs.size() * sizeof(SplitTileRec));
 
+  // Device memory: the caller's buffers (grown on demand), else the pool.
   void *dev = nullptr;
-  int rc = pool_alloc(&dev, wbytes + (int64_t)meta, s);
-  if (rc != MG_OK) return rc;
+  int rc = MG_OK;
+  if (buf != nullptr) {
+    rc = buf->reserve((size_t)wbytes + meta, meta);
+    if (rc != MG_OK) return rc;
+    dev = buf->d;
+  } else {
+    rc = pool_alloc(&dev, wbytes + (int64_t)meta, s);
+    if (rc != MG_OK) return rc;
+  }
   unsigned char *w = static_cast<unsigned char *>(dev);
   const int bits = split_bits(algo);
   for (int j = 0; j < nl; ++j) {
@@ -2006,8 +2044,10 @@ int gemm_split_batched(int algo, int64_t count, const mg_problem *probs, hipStre
     d.As = base + l.a_off;
     d.Bs = base + l.b_off;
   }
-  auto *host = new std::vector<unsigned char>(meta, 0);
-  unsigned char *h = host->data();
+  // Host staging: the caller's pinned buffer, else a heap copy kept until
+  // the stream has passed the copy.
+  std::vector<unsigned char> *host = buf ? nullptr : new std::vector<unsigned char>(meta, 0);
+  unsigned char *h = buf ? static_cast<unsigned char *>(buf->h) : host->data();
   std::memcpy(h + o_args, args.data(), args.size() * sizeof(SplitArgs));
   std::memcpy(h + o_desc, desc.data(), desc.size() * sizeof(SplitPrepDesc));
   std::memcpy(h + o_first, first.data(), first.size() * sizeof(int));
@@ -2029,6 +2069,7 @@ int gemm_split_batched(int algo, int64_t count, const mg_problem *probs, hipStre
              : launch_batched_t<MG_SPLIT_I8>(d_args, d_desc, d_first, nl, blocks, d_recs,
                                              (int)recs.size(), s);
   }
+  if (buf != nullptr) return rc;
   hipEvent_t ev = nullptr;
   if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess &&
       hipEventRecord(ev, s) == hipSuccess) {

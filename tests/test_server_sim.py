@@ -102,7 +102,10 @@ def test_continuous_batching_groups_late_arrivals():
         # ~17 ms modeled: the late requests all arrive while it runs, even on
         # a loaded host
         first = srv.submit_request(ops.request(2048))
-        time.sleep(0.0005)
+        deadline = time.time() + 5.0
+        while srv.stats()["batches"] < 1 and time.time() < deadline:
+            time.sleep(0.0002)  # the first request is taken as a batch of its own
+        assert srv.stats()["batches"] == 1
         late = [srv.submit_request(ops.request(64)) for _ in range(10)]
         r0 = srv.wait(first)
         rl = [srv.wait(t) for t in late]

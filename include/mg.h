@@ -373,7 +373,11 @@ int mg_gemm_batched_noalloc(int dtype, int64_t count, const mg_problem *probs, v
  * plus the split workspace for split requests) within `hbm_budget_bytes`, and
  * launches everything admitted so far as one batch on the next free stream
  * (one persistent grouped launch for the native requests, one batched split
- * launch set per split algorithm, as in mg_gemm_batched).  Batches on different streams run concurrently on the
+ * launch set per split algorithm, as in mg_gemm_batched; each stream keeps
+ * its own grow-only device workspace and pinned staging buffer for these,
+ * so a batch allocates only when it needs more than any batch before it on
+ * that stream; they are freed by mg_server_destroy).
+ * Batches on different streams run concurrently on the
  * device (the paper's scheduler may run grids from several streams in
  * parallel, Section 3.3); requests that arrive while batches run are admitted
  * as slots and bytes free up and go out with the next batch.  A request's

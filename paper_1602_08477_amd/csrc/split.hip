@@ -1892,7 +1892,11 @@ int gemm_split_batched(int algo, int64_t count, const mg_problem *probs, hipStre
     BLayout &l = L[(size_t)j];
     l.mr = round_up(q.m, TILE);
     l.nr = round_up(q.n, TILE);
-    l.kp = round_up(q.k, (int64_t)kSplitTileK);
+    // k padded to the all-pairs tile's 64-byte stage (INT8: 64 k, BF16: 32 k,
+    // rounded up to 64 k so that the preparation's 64 x 64 blocks tile it):
+    // zero slices past k add nothing, so the bits are those of the single
+    // call, which pads to 128.
+    l.kp = round_up(q.k, (int64_t)64);
     int64_t off = 0;
     l.e_off = off;
     off = round_up(off + 4 * l.mr, 256);

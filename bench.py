@@ -134,6 +134,24 @@ def time_interleaved(fns, steps, warmup, stream):
     return [[s.elapsed_time(e) for s, e in evs] for evs in out]
 
 
+def back_to_back_ms(fn, reps, stream, rounds=3):
+    """Mean per-launch time (ms) of `reps` launches issued back to back
+    between one pair of HIP events; the median over `rounds` such runs."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    res = []
+    for _ in range(rounds):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record(stream)
+        for _ in range(reps):
+            fn()
+        e.record(stream)
+        torch.cuda.synchronize()
+        res.append(s.elapsed_time(e) / reps)
+    return float(np.median(res))
+
+
 def bench_native(n, steps, warmup):
     import torch
     import paper_1602_08477_amd as mg
@@ -180,7 +198,8 @@ def bench_sizes(steps, warmup):
     cold time with the L2 and MALL flushed by a 512 MiB write before each
     launch.  For context only, the platform BLAS (in-place torch addmm_, one
     GEMM launch per call) is timed on the same operands, its launches
-    alternating with this library's."""
+    alternating with this library's; both are also timed with their
+    launches back to back (steady state, as the headline is timed)."""
     import torch
     import paper_1602_08477_amd as mg
     import synth
@@ -215,6 +234,14 @@ def bench_sizes(steps, warmup):
                "tflops": round(flop / ms / 1e9, 3),
                "pct_peak": round(100 * flop / ms / 1e9 / FP64_PEAK, 2),
                "context_torch_addmm_tflops": round(flop / ms_v / 1e9, 3)}
+        # steady state, as the headline is timed: launches back to back (no
+        # other kernel in between), one pair of events around a run of them
+        b2b = back_to_back_ms(fn, reps, stream)
+        b2b_v = back_to_back_ms(lambda: ref.addmm_(dA, dB, beta=beta, alpha=alpha), reps,
+                                stream)
+        rec["ms_back_to_back"] = round(b2b, 5)
+        rec["pct_peak_back_to_back"] = round(100 * flop / b2b / 1e9 / FP64_PEAK, 2)
+        rec["context_torch_addmm_tflops_back_to_back"] = round(flop / b2b_v / 1e9, 3)
         if max(m, n, k) <= 2048:
             cold = []
             for _ in range(reps):

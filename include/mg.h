@@ -340,7 +340,7 @@ int mg_plan_destroy(mg_plan *plan);
  * from them, with the diagonal sums and FP64 partial sums in registers
  * (Section 3.3: independent grids of one device run concurrently; here they
  * share one launch).  The per-problem workspaces (exponents and
- * slices padded to 64 rows / columns and 128 k, in one allocation from the
+ * slices padded to 64 rows / columns and 64 k, in one allocation from the
  * library's workspace pool, freed on `stream` after the batch) and the
  * descriptors are built per call; nothing is kept.  Each result equals
  * mg_gemm(MG_F64, algo, ...) on that problem alone, bit for bit.

@@ -184,15 +184,18 @@ __device__ __forceinline__ void slice_rows_exp_body(const double *A, int64_t lda
   }
 }
 
-// The same for rows of at most 1024 (padded) k with one wavefront per row:
-// a lane holds quads lane, lane + 64, lane + 128, lane + 192 in registers,
-// and the row's exponent is a wavefront reduction.  Row `i`.
-template <int ESZ>
+// The same for rows of at most 16 * LPR (padded) k with LPR lanes per row
+// (LPR = 16, 32 or 64: 4, 2 or 1 rows per wavefront): a lane holds quads l,
+// l + LPR, l + 2 LPR, l + 3 LPR of its row in registers (l = its index in
+// the row's lane group), and the row's exponent is a reduction over the
+// group.  This lane's row is `i`.
+template <int ESZ, int LPR>
 __device__ __forceinline__ void slice_rows_wave_body(const double *A, int64_t lda, int m, int k,
                                                      int mp, int64_t kp, int *E, int s, int bits,
                                                      unsigned char *out, int i) {
+  static_assert(LPR == 16 || LPR == 32 || LPR == 64, "lanes per row");
   constexpr int QPT = 4;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & (LPR - 1);
   const bool live = i < m;
   const double *row = A + (int64_t)(live ? i : 0) * lda;
   const int quads = (int)(kp / 4);
@@ -200,7 +203,7 @@ __device__ __forceinline__ void slice_rows_wave_body(const double *A, int64_t ld
   int e = INT_MIN;
 #pragma unroll
   for (int j = 0; j < QPT; ++j) {
-    const int qd = lane + 64 * j;
+    const int qd = lane + LPR * j;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int kk = qd * 4 + v;
@@ -210,13 +213,13 @@ __device__ __forceinline__ void slice_rows_wave_body(const double *A, int64_t ld
     }
   }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) e = max(e, __shfl_xor(e, off));
+  for (int off = LPR / 2; off > 0; off >>= 1) e = max(e, __shfl_xor(e, off));
   const int ei = (e == INT_MIN) ? 0 : e;
   if (lane == 0) E[i] = ei;
   const int64_t slice_bytes = (int64_t)mp * kp * ESZ;
 #pragma unroll
   for (int j = 0; j < QPT; ++j) {
-    const int qd = lane + 64 * j;
+    const int qd = lane + LPR * j;
     if (qd >= quads) continue;
     double r[4];
 #pragma unroll
@@ -1114,7 +1117,8 @@ struct SplitPrepDesc {
   int m, n, k, mp, np;
   int nr;      // columns of B the product tiles read: n rounded up to the tile
   int cx, cy;  // column-exponent blocks: cx blocks of 256 columns x cy k-chunk strides
-  int rpb;     // rows of A per block: 4 (one per wavefront, kp <= 1024) or 1
+  int rpb;     // rows of A per block: 16, 8, 4 (4, 2, 1 per wavefront; kp <= 256, 512,
+               // 1024) or 1
   int *E, *F;
   unsigned char *As, *Bs;
 };
@@ -1155,9 +1159,15 @@ __global__ __launch_bounds__(256) void batched_exp_rows_kernel(const SplitPrepDe
     col_exp_body(q.B, q.ldb, q.k, q.n, q.F, lb % q.cx, lb / q.cx, q.cy);
   else if (q.rpb == 1)
     slice_rows_exp_body<ESZ>(q.A, q.lda, q.m, q.k, q.mp, q.kp, q.E, s, bits, q.As, lb - ncol);
+  else if (q.rpb == 16)
+    slice_rows_wave_body<ESZ, 16>(q.A, q.lda, q.m, q.k, q.mp, q.kp, q.E, s, bits, q.As,
+                                  (lb - ncol) * 16 + (int)(threadIdx.x >> 4));
+  else if (q.rpb == 8)
+    slice_rows_wave_body<ESZ, 32>(q.A, q.lda, q.m, q.k, q.mp, q.kp, q.E, s, bits, q.As,
+                                  (lb - ncol) * 8 + (int)(threadIdx.x >> 5));
   else
-    slice_rows_wave_body<ESZ>(q.A, q.lda, q.m, q.k, q.mp, q.kp, q.E, s, bits, q.As,
-                              (lb - ncol) * 4 + (int)(threadIdx.x >> 6));
+    slice_rows_wave_body<ESZ, 64>(q.A, q.lda, q.m, q.k, q.mp, q.kp, q.E, s, bits, q.As,
+                                  (lb - ncol) * 4 + (int)(threadIdx.x >> 6));
 }
 
 template <int ESZ>
@@ -1845,6 +1855,13 @@ void SplitBatchBuffers::release() {
   d_cap = h_cap = 0;
 }
 
+// Rows of A per preparation block of the batched path (256 lanes): short
+// rows share a wavefront (16 lanes per row up to 256 k, 32 up to 512, 64 up
+// to 1024); longer rows take a whole block each.
+static int64_t rows_per_block(int64_t kp) {
+  return kp <= 256 ? 16 : kp <= 512 ? 8 : kp <= 1024 ? 4 : 1;
+}
+
 int gemm_split_batched(int algo, int64_t count, const mg_problem *probs, hipStream_t s,
                        SplitBatchBuffers *buf) {
   if (algo != MG_SPLIT_I8 && algo != MG_SPLIT_BF16) {
@@ -1928,7 +1945,7 @@ int gemm_split_batched(int algo, int64_t count, const mg_problem *probs, hipStre
     const BLayout &l = L[(size_t)j];
     const int64_t nchunks = ceil_div(q.k, kColRows);
     const int64_t cx = ceil_div(q.n, 256), cy = std::min<int64_t>(nchunks, 256);
-    const int64_t rpb = l.kp <= 1024 ? 4 : 1;
+    const int64_t rpb = rows_per_block(l.kp);
     const int64_t nb[3] = {ceil_div(l.nr, 256), cx * cy + l.mr / rpb, (l.nr / 64) * (l.kp / 64)};
     for (int w = 0; w < 3; ++w) {
       first[(size_t)w * (nl + 1) + j] = (int)blocks[w];
@@ -2042,7 +2059,7 @@ int gemm_split_batched(int algo, int64_t count, const mg_problem *probs, hipStre
     d.nr = (int)l.nr;
     d.cx = (int)ceil_div(q.n, 256);
     d.cy = (int)std::min<int64_t>(ceil_div(q.k, kColRows), 256);
-    d.rpb = l.kp <= 1024 ? 4 : 1;
+    d.rpb = (int)rows_per_block(l.kp);
     d.E = reinterpret_cast<int *>(base + l.e_off);
     d.F = reinterpret_cast<int *>(base + l.f_off);
     d.As = base + l.a_off;

@@ -1584,13 +1584,16 @@ int split_num_cfgs() { return 17; }
 // register-staged 128x128 tile.
 int split_pick_cfg(int algo, int slices, int64_t mp, int64_t np, bool latency) {
   // For one call's latency, at the default slice count, the all-pairs 64x64
-  // tile (16) up to n = 2048 (INT8) / 1024 (BF16): whole INT8 call n = 256 /
-  // 512 / 1024 / 2048: 50 / 57 / 90 / 304 us against 76 / 100 / 139 / 428
-  // for the pair-parallel division and the 128x128 ring; at n = 4096 2.17
-  // against 1.89 ms for the 256x256 ring.  BF16 n = 1024: 163 against 223 us;
-  // n = 2048: 632 against 554.
+  // tile (16): INT8 at every size, BF16 up to n = 1024.  Whole INT8 call n =
+  // 256 / 512 / 1024: 50 / 57 / 90 us against 76 / 100 / 139 for the
+  // pair-parallel division and the 128x128 ring; products with a held
+  // workspace, n = 2048 / 3072 / 4096 / 5120 / 6144 / 8192: 0.21 / 0.73 /
+  // 1.61 / 3.17 / 5.52 / 11.99 ms against 0.23 / 1.57 / 1.78 / 4.20 / 7.33 /
+  // 12.69 for the 256x256 ring (whose tiles fill the chip only at n = 4096
+  // and 8192).  BF16 n = 1024: 163 against 223 us; n = 2048 / 3072 about
+  // even, n = 4096 4.24 against 3.19 ms (its FP32-to-INT32 conversions).
   if (latency && slices == split_default_slices(algo) &&
-      mp * np <= (algo == MG_SPLIT_BF16 ? (int64_t)1024 * 1024 : (int64_t)2048 * 2048))
+      (algo == MG_SPLIT_I8 || mp * np <= (int64_t)1024 * 1024))
     return 16;
   // Other slice counts below one 128x128 tile per CU: the pair-parallel
   // division (15): the fused divisions would give too few workgroups, each

@@ -209,8 +209,8 @@ int mg_gemm_split(int algo, int slices, int64_t m, int64_t n, int64_t k, double 
  * LDS and forms all slice pairs from it, one exact INT32 sum per diagonal and
  * the FP64 partial sums in registers, two workgroups per CU (needs no
  * partial-sum region: p_off bytes of workspace suffice).  mg_gemm_split and
- * mg_gemm pick by size (16 up to n = 2048 INT8 / 1024 BF16 at the default
- * slice count); mg_gemm_split_cfg takes cfg explicitly (-1 = pick).
+ * mg_gemm pick by size (16 at the default slice count: INT8 at every size,
+ * BF16 up to n = 1024); mg_gemm_split_cfg takes cfg explicitly (-1 = pick).
  * MG_ERR_INVALID_ARG for an unknown cfg. */
 int mg_split_num_cfgs(void);
 int mg_gemm_split_cfg(int algo, int slices, int cfg, int64_t m, int64_t n, int64_t k,

@@ -213,6 +213,33 @@ def test_config3_n4096_sampled(kind):
     assert np.array_equal(got, want)
 
 
+def test_int8_default_large_ragged_matches_other_division_and_oracle():
+    """INT8 single calls take the all-pairs 64x64 tile at every size: on a
+    large ragged shape its result equals the 256x256 ring's (division 4) bit
+    for bit, and sampled rows/columns equal the oracle's split result and
+    lie within 1e-12 of the exact product."""
+    m, n, k = 3000, 2500, 1100
+    algo = ALGOS["i8"]
+    s = mg.split_default_slices(algo)
+    A, B, C = spread(61, m, n, k)
+    dA, dB = to_dev(A), to_dev(B)
+    c_pick, c_ring = to_dev(C), to_dev(C)
+    mg.gemm(dA, dB, c_pick, 1.5, 0.5, algo=algo)
+    mg.gemm_split(dA, dB, c_ring, 1.5, 0.5, algo=algo, slices=s, cfg=4)
+    torch.cuda.synchronize()
+    assert torch.equal(c_pick, c_ring)
+    rows = np.unique(np.concatenate([[0, m - 1], synth.log_uniform_int(61, 9, 20, 1, m - 1)]))
+    cols = np.unique(np.concatenate([[0, n - 1], synth.log_uniform_int(61, 10, 20, 1, n - 1)]))
+    got = c_pick.cpu().numpy()[np.ix_(rows, cols)]
+    Cs = C[np.ix_(rows, cols)]
+    # row scales depend on whole rows of A, column scales on whole columns of B
+    want = osplit.split_gemm(1.5, A[rows], B[:, cols], 0.5, Cs, s, "i8")
+    assert np.array_equal(got, want)
+    err = oracle.rel_fro_err(got, oracle.dgemm(1.5, A[rows], B[:, cols], 0.5, Cs))
+    log(f"split i8 {(m, n, k)} default pick: sampled rel_fro_err={err:.3e}")
+    assert err <= 1e-12
+
+
 def test_workspace_below_operands_is_not_an_overlap():
     """Regression: a workspace at lower addresses than the operands (allocated
     first) was once reported as overlapping them."""

@@ -53,7 +53,7 @@ __global__ void fill_int_kernel(int *p, int count, int v) {
   fill_int_body(p, count, v, blockIdx.x);
 }
 
-constexpr int kColRows = 64;  // rows of B per thread in col_exp_kernel
+constexpr int kColRows = 64;  // rows of B per thread in col_exp_body
 
 // Column exponents of B for the 256 columns of block `bx`, over the k chunks
 // by, by + gy, ... (the maximum is order-independent).
@@ -71,9 +71,6 @@ __device__ __forceinline__ void col_exp_body(const double *B, int64_t ldb, int k
   }
 }
 
-__global__ void col_exp_kernel(const double *B, int64_t ldb, int k, int n, int *F) {
-  col_exp_body(B, ldb, k, n, F, blockIdx.x, blockIdx.y, gridDim.y);
-}
 
 // ------------------------------------------------------------ step 2: slices
 // Packs CW slice values (CW*ESZ == 16 bytes) into one 16-byte store.
@@ -242,11 +239,19 @@ __device__ __forceinline__ void slice_rows_wave_body(const double *A, int64_t ld
   }
 }
 
+// Steps 1 and 2 without B's slices in one launch: blocks [0, cx*cy) find
+// B's column exponents (col_exp_body), the rest each find one row's
+// exponent of A and slice it.  The two passes are independent, so they run
+// side by side instead of one after the other.
 template <int ESZ>
-__global__ __launch_bounds__(256) void slice_rows_exp_kernel(const double *A, int64_t lda, int m,
-                                                             int k, int mp, int64_t kp, int *E,
-                                                             int s, int bits, unsigned char *out) {
-  slice_rows_exp_body<ESZ>(A, lda, m, k, mp, kp, E, s, bits, out, blockIdx.x);
+__global__ __launch_bounds__(256) void exp_rows_kernel(const double *A, int64_t lda, int m, int k,
+                                                       int mp, int64_t kp, int *E, int s, int bits,
+                                                       unsigned char *out, const double *B,
+                                                       int64_t ldb, int n, int *F, int cx,
+                                                       int cy) {
+  const int b = (int)blockIdx.x, ncol = cx * cy;
+  if (b < ncol) col_exp_body(B, ldb, k, n, F, b % cx, b / cx, cy);
+  else slice_rows_exp_body<ESZ>(A, lda, m, k, mp, kp, E, s, bits, out, b - ncol);
 }
 
 // B slices, stored transposed [s][np][kp] (k contiguous per column of B):
@@ -1546,30 +1551,29 @@ int split_prepare(int algo, int slices, int64_t m, int64_t n, int64_t k, const d
 
   hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)ceil_div(np, 256)), dim3(256), 0, s, F, np,
                      INT_MIN);
-  if (n > 0 && k > 0) {
-    const int64_t nchunks = ceil_div(k, kColRows);
-    hipLaunchKernelGGL(col_exp_kernel,
-                       dim3((unsigned)ceil_div(n, 256), (unsigned)std::min<int64_t>(nchunks, 4096)),
-                       dim3(256), 0, s, B, ldb, (int)k, (int)n, F);
-  }
   MG_HIP_TRY(hipGetLastError());
+  // column-exponent blocks of B (none when B is empty)
+  const int64_t cx = n > 0 && k > 0 ? ceil_div(n, 256) : 0;
+  const int64_t cy = n > 0 && k > 0 ? std::min<int64_t>(ceil_div(k, kColRows), 4096) : 0;
 
   unsigned char *As = w + L.a_off, *Bs = w + L.b_off;
   const int64_t cblocks = (L.np / 64) * (L.kp / 64);
   // one workgroup of 256 lanes per row / per 64 x 64 block; the dispatch's
   // work-item count is 32-bit
-  if (cblocks * 256 > (int64_t)UINT32_MAX || (int64_t)mp * 256 > (int64_t)UINT32_MAX) {
+  if (cblocks * 256 > (int64_t)UINT32_MAX || (cx * cy + mp) * 256 > (int64_t)UINT32_MAX) {
     set_error("split operands too large for one dispatch");
     return MG_ERR_INVALID_ARG;
   }
   if (algo == MG_SPLIT_BF16) {
-    hipLaunchKernelGGL(slice_rows_exp_kernel<2>, dim3((unsigned)mp), dim3(256), 0, s, A, lda,
-                       (int)m, (int)k, mp, L.kp, E, slices, bits, As);
+    hipLaunchKernelGGL(exp_rows_kernel<2>, dim3((unsigned)(cx * cy + mp)), dim3(256), 0, s, A,
+                       lda, (int)m, (int)k, mp, L.kp, E, slices, bits, As, B, ldb, (int)n, F,
+                       (int)cx, (int)cy);
     hipLaunchKernelGGL(slice_cols_kernel<2>, dim3((unsigned)cblocks), dim3(256), 0, s, B, ldb,
                        (int)k, (int)n, np, L.kp, F, slices, bits, Bs);
   } else {
-    hipLaunchKernelGGL(slice_rows_exp_kernel<1>, dim3((unsigned)mp), dim3(256), 0, s, A, lda,
-                       (int)m, (int)k, mp, L.kp, E, slices, bits, As);
+    hipLaunchKernelGGL(exp_rows_kernel<1>, dim3((unsigned)(cx * cy + mp)), dim3(256), 0, s, A,
+                       lda, (int)m, (int)k, mp, L.kp, E, slices, bits, As, B, ldb, (int)n, F,
+                       (int)cx, (int)cy);
     hipLaunchKernelGGL(slice_cols_kernel<1>, dim3((unsigned)cblocks), dim3(256), 0, s, B, ldb,
                        (int)k, (int)n, np, L.kp, F, slices, bits, Bs);
   }

@@ -932,7 +932,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the GEMM path "
-              "here is single-GPU; see DESIGN.md for how it would shard.", file=sys.stderr)
+              "here is single-GPU; sharding it over GPUs is not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch
